@@ -1,0 +1,148 @@
+/*
+ * osht.h -- C ABI of the MI355X implementation of the forward and inverse
+ * spherical harmonic transform on the optimal-dimensionality L^2-sample
+ * scheme of Khalid, Kennedy & McEwen (IEEE TSP 2014).
+ *
+ * Geometry (Sec. III-A): L iso-latitude rings; ring k (k = 0..L-1) sits at
+ * colatitude theta_k = pi n_k / (2L-1), n_k an odd integer numerator
+ * (Eq. equiangular_set), and carries 2k+1 samples at phi_j = 2 pi j/(2k+1).
+ * The sample vector of one map therefore has exactly L^2 entries
+ * (Eq. number_samples_sum), as does the coefficient vector.
+ *
+ * Array layouts (all arrays are complex128, interleaved re/im doubles):
+ *   samples       f[b * L*L + k*k + j]          ring-major, j = 0..2k
+ *   coefficients  flm[b * L*L + l*l + l + m]     l-major, 0 <= l < L, |m| <= l
+ * b = 0..batch-1 indexes maps.  For spin s, coefficients with l < |s| do not
+ * exist: inputs must hold zeros there and outputs are written as zeros.
+ *
+ * Ownership: a plan owns all of its device memory (placement, Legendre
+ * blocks, factorised per-order inverses, workspace) on the HIP device that
+ * was current at osht_plan_create.  Transform entry points take caller-owned
+ * DEVICE pointers, enqueue work on the given stream and return without
+ * synchronising.  Calls on one plan must not overlap in time (the plan's
+ * workspace is shared by all of its calls): serialise them on one stream.
+ *
+ * Errors: every entry point returns OSHT_OK (0) or a negative OSHT_E* code;
+ * osht_strerror() gives a message.  Argument errors are detected on the host
+ * before any work is enqueued.
+ */
+#ifndef OSHT_H
+#define OSHT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+#define OSHT_OK            0
+#define OSHT_EINVAL       -1  /* bad argument (L, spin, batch, pointer, aliasing) */
+#define OSHT_ENOMEM       -2  /* device or host allocation failed */
+#define OSHT_EHIP         -3  /* a HIP runtime call failed */
+#define OSHT_ESINGULAR    -4  /* a per-order system P_m failed its inversion check */
+#define OSHT_ENOTSUP      -5  /* combination of flags not supported */
+#define OSHT_EIO          -6  /* placement cache file unreadable or malformed */
+
+/* ------------------------------------------------------------------ flags */
+/* arithmetic of the order-wise apply */
+#define OSHT_PREC_FP64        0x0u   /* FP64 throughout */
+#define OSHT_PREC_MASK        0x0fu
+/* colatitude placement (Sec. III-D) */
+#define OSHT_THETA_GREEDY       0x00u  /* condition-number-minimising greedy */
+#define OSHT_THETA_ALTERNATING  0x10u  /* Eq. sampling_latitude */
+#define OSHT_THETA_MASK         0xf0u
+
+typedef struct osht_plan osht_plan_t;
+
+typedef struct {
+  int32_t  L;
+  int32_t  spin;
+  uint32_t flags;
+  int32_t  reserved;
+  int64_t  nsamples;        /* L*L per map */
+  int64_t  ncoeffs;         /* L*L per map */
+  int64_t  device_bytes;    /* device memory held by the plan */
+  double   max_kappa;       /* max over m of cond_2 estimate of P_m */
+  double   max_inv_residual;/* max over m of |I - X_m P_m|_max after inversion */
+} osht_info_t;
+
+/*
+ * Colatitude placement, computed on the host, no GPU needed.
+ * Greedy (Sec. III-D): theta_{L-1} is the member of Theta farthest from the
+ * poles; for m = L-2 down to 0, theta_m is the unused member of Theta that
+ * minimises cond_2(P_m) (Eq. Y_matrix built from rings m..L-1 and degrees
+ * m..L-1); candidates within a relative 1e-12 of the minimum are tied and
+ * the smallest numerator wins.
+ *   numerators_out: host array of L int32, receives n_k (ring k).
+ *   kappa_out:      host array of L doubles or NULL; receives cond_2(P_m).
+ * Returns OSHT_EINVAL for L < 1 or a NULL output array.
+ */
+int osht_theta_greedy(int L, int32_t* numerators_out, double* kappa_out);
+/* Eq. sampling_latitude: even k take 2L-1-k, odd k take k. */
+int osht_theta_alternating(int L, int32_t* numerators_out);
+
+/*
+ * Build a plan for band-limit L (1 <= L <= 4096) and spin s (|s| < L).
+ * theta_cache_dir (nullable): directory holding placement files named
+ * "theta_greedy_L<L>.txt" (one numerator per line, '#' lines ignored);
+ * read if present, otherwise the greedy is run on the host and the file is
+ * written there (write failures are ignored).
+ * On the current HIP device: evaluates the Legendre (or Wigner) blocks
+ * A_m[k, i] = sY_{l0+i}^m(theta_k, 0) in FP64 with adaptive rescaling
+ * (Sec. III-F, III-G), inverts every P_m (rows k >= |m| of A_m; the least
+ * squares pseudo-inverse when |m| < |s|) in FP64 on the GPU, and checks
+ * |I - X_m P_m|_max < 1e-6 for each m (else OSHT_ESINGULAR).
+ * Synchronous: returns once the plan is ready.  *out receives the plan.
+ */
+int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_dir,
+                     osht_plan_t** out);
+/* Frees everything the plan owns. NULL is accepted. */
+int osht_plan_destroy(osht_plan_t* plan);
+int osht_plan_info(const osht_plan_t* plan, osht_info_t* out);
+/* Copies the L ring numerators n_k (theta_k = pi n_k/(2L-1)) to host memory. */
+int osht_plan_theta(const osht_plan_t* plan, int32_t* numerators_host);
+
+/*
+ * Inverse SHT (Eq. f_inverse_SHT, Procedure 2): samples from coefficients.
+ *   flm: device, batch * L*L complex128 (read)
+ *   f:   device, batch * L*L complex128 (written); must not overlap flm.
+ * batch >= 1.  Asynchronous on stream.
+ */
+int osht_inverse(const osht_plan_t* plan, const void* flm, void* f, int64_t batch,
+                 hipStream_t stream);
+
+/*
+ * Forward SHT (Procedure 1): coefficients from samples, removing the
+ * aliases of orders |m'| > |m| in descending |m| before the order-m systems
+ * P_m f_m = g_m are solved (Eq. gtof_inverse, Eq. signal_update).
+ *   f:   device, batch * L*L complex128 (read)
+ *   flm: device, batch * L*L complex128 (written); must not overlap f.
+ */
+int osht_forward(const osht_plan_t* plan, const void* f, void* flm, int64_t batch,
+                 hipStream_t stream);
+
+/*
+ * Adjoints: exact conjugate transposes of the two maps above with respect to
+ * the Euclidean inner product on C^{L^2} (samples and coefficients alike).
+ *   inverse_adjoint: f_bar (samples)     -> flm_bar (coefficients)
+ *   forward_adjoint: flm_bar (coefficients) -> f_bar (samples)
+ * Same layouts, ownership and stream semantics as the transforms.
+ */
+int osht_inverse_adjoint(const osht_plan_t* plan, const void* f_bar, void* flm_bar,
+                         int64_t batch, hipStream_t stream);
+int osht_forward_adjoint(const osht_plan_t* plan, const void* flm_bar, void* f_bar,
+                         int64_t batch, hipStream_t stream);
+
+/* Human-readable message for a return code (static storage). */
+const char* osht_strerror(int code);
+/* Detail of the last error raised on the calling thread (thread-local
+ * storage, valid until the next call on that thread). */
+const char* osht_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OSHT_H */

@@ -1,0 +1,248 @@
+// extern "C" entry points of libosht (declared in include/osht.h).
+
+#include <unistd.h>
+
+#include <cerrno>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+
+#include "common.hpp"
+#include "host_util.hpp"
+
+using osht::Error;
+using osht::Plan;
+
+struct osht_plan {
+  Plan p;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+bool valid_permutation(int L, const std::vector<int32_t>& num) {
+  if ((int)num.size() != L) return false;
+  std::vector<char> seen(L, 0);
+  for (int32_t n : num) {
+    if (n < 1 || n > 2 * L - 1 || (n % 2) == 0) return false;
+    if (seen[(n - 1) / 2]) return false;
+    seen[(n - 1) / 2] = 1;
+  }
+  return true;
+}
+
+std::string cache_path(const char* dir, int L) {
+  return std::string(dir) + "/theta_greedy_L" + std::to_string(L) + ".txt";
+}
+
+// 1: read ok, 0: no file, -1: malformed
+int read_cache(const std::string& path, int L, std::vector<int32_t>& num) {
+  std::ifstream in(path);
+  if (!in) return 0;
+  num.clear();
+  std::string line;
+  while (std::getline(in, line)) {
+    size_t a = line.find_first_not_of(" \t\r");
+    if (a == std::string::npos || line[a] == '#') continue;
+    char* end = nullptr;
+    long v = std::strtol(line.c_str() + a, &end, 10);
+    if (end == line.c_str() + a) return -1;
+    num.push_back((int32_t)v);
+  }
+  return valid_permutation(L, num) ? 1 : -1;
+}
+
+void write_cache(const std::string& path, const std::vector<int32_t>& num, const std::vector<double>& kap) {
+  std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+  std::ofstream out(tmp);
+  if (!out) return;
+  for (int32_t n : num) out << n << "\n";
+  double km = 0.0;
+  for (double k : kap) km = std::max(km, k);
+  char buf[64];
+  std::snprintf(buf, sizeof buf, "# max_kappa %.6e\n", km);
+  out << buf;
+  out.close();
+  if (out) std::rename(tmp.c_str(), path.c_str());
+  else std::remove(tmp.c_str());
+}
+
+bool overlaps(const void* a, const void* b, size_t bytes) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <class Fn>
+int run_transform(const osht_plan_t* plan, const void* in, void* out, int64_t batch, Fn fn) {
+  if (!plan) return fail(OSHT_EINVAL, "plan is NULL");
+  if (!in || !out) return fail(OSHT_EINVAL, "input or output pointer is NULL");
+  if (batch < 1 || batch > 65535) return fail(OSHT_EINVAL, "batch must be in [1, 65535]");
+  Plan& p = const_cast<osht_plan_t*>(plan)->p;
+  const size_t bytes = sizeof(double) * 2 * (size_t)p.L * p.L * (size_t)batch;
+  if (overlaps(in, out, bytes)) return fail(OSHT_EINVAL, "input and output buffers overlap");
+  try {
+    std::lock_guard<std::mutex> lk(p.mu);
+    DeviceGuard g(p.device);
+    fn(p, static_cast<const double*>(in), static_cast<double*>(out));
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(OSHT_ENOMEM, "host allocation failed");
+  }
+  return OSHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* osht_strerror(int code) {
+  switch (code) {
+    case OSHT_OK: return "success";
+    case OSHT_EINVAL: return "invalid argument";
+    case OSHT_ENOMEM: return "out of memory";
+    case OSHT_EHIP: return "HIP runtime error";
+    case OSHT_ESINGULAR: return "a per-order system failed its inversion check";
+    case OSHT_ENOTSUP: return "unsupported flag combination";
+    case OSHT_EIO: return "placement cache file unreadable or malformed";
+    default: return "unknown error";
+  }
+}
+
+const char* osht_last_error_message(void) { return g_last_error.c_str(); }
+
+int osht_theta_greedy(int L, int32_t* numerators_out, double* kappa_out) {
+  if (L < 1 || L > 4096 || !numerators_out) return fail(OSHT_EINVAL, "L must be in [1, 4096] and the output non-NULL");
+  try {
+    osht::theta_greedy(L, numerators_out, kappa_out);
+  } catch (const std::bad_alloc&) {
+    return fail(OSHT_ENOMEM, "host allocation failed");
+  }
+  return OSHT_OK;
+}
+
+int osht_theta_alternating(int L, int32_t* numerators_out) {
+  if (L < 1 || L > 4096 || !numerators_out) return fail(OSHT_EINVAL, "L must be in [1, 4096] and the output non-NULL");
+  osht::theta_alternating(L, numerators_out);
+  return OSHT_OK;
+}
+
+int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_dir, osht_plan_t** out) {
+  if (!out) return fail(OSHT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (L < 1 || L > 4096) return fail(OSHT_EINVAL, "L must be in [1, 4096]");
+  if (spin <= -L || spin >= L) return fail(OSHT_EINVAL, "|spin| must be < L");
+  const uint32_t prec = flags & OSHT_PREC_MASK, theta = flags & OSHT_THETA_MASK;
+  if (prec != OSHT_PREC_FP64) return fail(OSHT_ENOTSUP, "only OSHT_PREC_FP64 is available");
+  if (theta != OSHT_THETA_GREEDY && theta != OSHT_THETA_ALTERNATING) return fail(OSHT_EINVAL, "unknown placement flag");
+  if (flags & ~(OSHT_PREC_MASK | OSHT_THETA_MASK)) return fail(OSHT_EINVAL, "unknown flag bits");
+  osht_plan_t* h = nullptr;
+  try {
+    h = new osht_plan_t;
+    Plan& p = h->p;
+    p.L = L;
+    p.spin = spin;
+    p.flags = flags;
+    OSHT_HIP(hipGetDevice(&p.device));
+    p.numer.assign(L, 0);
+    if (theta == OSHT_THETA_ALTERNATING) {
+      osht::theta_alternating(L, p.numer.data());
+    } else {
+      int got = 0;
+      if (theta_cache_dir) {
+        got = read_cache(cache_path(theta_cache_dir, L), L, p.numer);
+        if (got < 0) throw Error{OSHT_EIO, "malformed placement cache " + cache_path(theta_cache_dir, L)};
+      }
+      if (got == 0) {
+        std::vector<double> kap(L);
+        p.numer.assign(L, 0);
+        osht::theta_greedy(L, p.numer.data(), kap.data());
+        if (theta_cache_dir) write_cache(cache_path(theta_cache_dir, L), p.numer, kap);
+      }
+    }
+    osht::build_plan(p);
+  } catch (const Error& e) {
+    delete h;
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    delete h;
+    return fail(OSHT_ENOMEM, "host allocation failed");
+  }
+  *out = h;
+  return OSHT_OK;
+}
+
+int osht_plan_destroy(osht_plan_t* plan) {
+  if (!plan) return OSHT_OK;
+  {
+    DeviceGuard g(plan->p.device);
+    (void)hipDeviceSynchronize();
+    delete plan;
+  }
+  return OSHT_OK;
+}
+
+int osht_plan_info(const osht_plan_t* plan, osht_info_t* out) {
+  if (!plan || !out) return fail(OSHT_EINVAL, "NULL argument");
+  const Plan& p = plan->p;
+  std::memset(out, 0, sizeof *out);
+  out->L = p.L;
+  out->spin = p.spin;
+  out->flags = p.flags;
+  out->nsamples = (int64_t)p.L * p.L;
+  out->ncoeffs = (int64_t)p.L * p.L;
+  out->device_bytes = p.device_bytes();
+  out->max_kappa = p.max_kappa;
+  out->max_inv_residual = p.max_resid;
+  return OSHT_OK;
+}
+
+int osht_plan_theta(const osht_plan_t* plan, int32_t* numerators_host) {
+  if (!plan || !numerators_host) return fail(OSHT_EINVAL, "NULL argument");
+  std::memcpy(numerators_host, plan->p.numer.data(), sizeof(int32_t) * plan->p.L);
+  return OSHT_OK;
+}
+
+int osht_inverse(const osht_plan_t* plan, const void* flm, void* f, int64_t batch, hipStream_t stream) {
+  return run_transform(plan, flm, f, batch,
+                       [&](Plan& p, const double* a, double* b) { osht::run_inverse(p, a, b, batch, stream); });
+}
+
+int osht_forward(const osht_plan_t* plan, const void* f, void* flm, int64_t batch, hipStream_t stream) {
+  return run_transform(plan, f, flm, batch,
+                       [&](Plan& p, const double* a, double* b) { osht::run_forward(p, a, b, batch, stream); });
+}
+
+int osht_inverse_adjoint(const osht_plan_t* plan, const void* f_bar, void* flm_bar, int64_t batch, hipStream_t stream) {
+  return run_transform(plan, f_bar, flm_bar, batch,
+                       [&](Plan& p, const double* a, double* b) { osht::run_inverse_adjoint(p, a, b, batch, stream); });
+}
+
+int osht_forward_adjoint(const osht_plan_t* plan, const void* flm_bar, void* f_bar, int64_t batch, hipStream_t stream) {
+  return run_transform(plan, flm_bar, f_bar, batch,
+                       [&](Plan& p, const double* a, double* b) { osht::run_forward_adjoint(p, a, b, batch, stream); });
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Internal declarations shared by the HIP sources of libosht.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/osht.h"
+
+namespace osht {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define OSHT_HIP(call)                                                            \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      throw ::osht::Error{e_ == hipErrorOutOfMemory ? OSHT_ENOMEM : OSHT_EHIP,    \
+                          std::string(#call) + ": " + hipGetErrorString(e_)};     \
+    }                                                                             \
+  } while (0)
+
+#define OSHT_CHECK(cond, code, what)                                              \
+  do {                                                                            \
+    if (!(cond)) throw ::osht::Error{(code), (what)};                             \
+  } while (0)
+
+// Owning device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) return;
+    OSHT_HIP(hipMalloc(&p, n));
+    bytes = n;
+  }
+  // grows (never shrinks); contents are not preserved
+  void reserve(size_t n) {
+    if (n > bytes) alloc(n);
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+template <class T>
+void upload(DevBuf& d, const std::vector<T>& h) {
+  d.alloc(h.size() * sizeof(T));
+  if (!h.empty()) OSHT_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// ---------------------------------------------------------------- plan
+// One "slot" per order handled by one matrix.  Spin 0: slot am covers the
+// two orders +am and -am (P_{-m} = (-1)^m P_m), RHS columns [+am | -am].
+// Spin s != 0: slot = m + L - 1 covers the single signed order m.
+struct Slot {
+  int32_t m;     // signed order (spin 0: am >= 0)
+  int32_t l0;    // first degree max(|m|, |s|)
+  int32_t K;     // unknowns L - l0
+  int32_t R;     // system rows L - |m| (rings |m| .. L-1)
+  int64_t offA;  // A_slot: L x K, column-major, leading dim ldA
+  int32_t ldA;
+  int32_t ldQ;   // Q_slot: (K + |m|) x R, column-major
+  int64_t offQ;
+};
+
+// Batched GEMM descriptor: C(MxN) = alpha * A(MxK) * B(KxN) + beta * C,
+// element (i, j) of X at X[i * sXr + j * sXc].
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t sAr, sAc, sBr, sBc, sCr, sCc;
+  int32_t M, N, K, pad;
+  double alpha, beta;
+};
+
+struct GemmTask {
+  int32_t desc, mt, nt, pad;
+};
+
+// Ring DFT geometry: ring k has n = 2k+1 samples; Bluestein size M_k.
+struct RingDesc {
+  int32_t n;      // 2k+1
+  int32_t logM;   // log2 of the Bluestein FFT size
+  int64_t off;    // offset of the chirp spectrum (M complex) in chirp table
+};
+
+struct Plan {
+  int L = 0, spin = 0;
+  uint32_t flags = 0;
+  int device = 0;
+  int nslots = 0;
+  int ncols_per_map = 0;  // 4 (spin 0: +/- x re/im) or 2
+  std::vector<int32_t> numer;
+  std::vector<Slot> slots;
+  double max_kappa = 0.0, max_resid = 0.0;
+  // device memory
+  DevBuf d_cos, d_sin, d_cosh, d_sinh;
+  DevBuf d_slots;
+  DevBuf d_A, d_Q;            // FP64 blocks
+  DevBuf d_rings, d_chirp, d_twiddle;
+  int max_logM = 0;
+  // per-call workspace (grown on demand)
+  DevBuf w_X, w_Y, w_H, w_T;
+  DevBuf d_gdesc, d_gtask;    // GEMM descriptors for the transforms
+  int64_t ws_batch = 0;
+  std::vector<GemmDesc> h_gdesc;
+  std::vector<GemmTask> h_gtask;
+  std::mutex mu;
+  int64_t device_bytes() const;
+};
+
+// ---------------------------------------------------------------- launchers
+// plan construction (plan.hip)
+void build_plan(Plan& p);
+// transforms (transform.hip)
+void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t st);
+void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st);
+void run_inverse_adjoint(Plan& p, const double* fbar, double* flmbar, int64_t B, hipStream_t st);
+void run_forward_adjoint(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st);
+
+// GEMM (gemm.hip): tasks and descriptors already on the device.
+void launch_gemm_f64(const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st);
+// Builds tasks for descriptors (64 x 64 tiles).
+void gemm_tasks(const std::vector<GemmDesc>& descs, std::vector<GemmTask>& tasks);
+
+// ring DFTs (dft.hip)
+void build_chirps(Plan& p);
+// samples [b][L^2] -> bins [L^2][B] (normalised analysis, scale 1/n_k) or
+// unnormalised (scale 1)
+void launch_ring_analysis(const Plan& p, const double* f, double* H, int64_t B, bool normalise,
+                          hipStream_t st);
+
+// placement (theta.cpp)
+int theta_greedy(int L, int32_t* num_out, double* kappa_out);
+void theta_alternating(int L, int32_t* num_out);
+
+constexpr int kTile = 64;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int round_up(int a, int b) { return (int)ceil_div(a, b) * b; }
+
+}  // namespace osht

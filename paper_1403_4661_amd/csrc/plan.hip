@@ -1,0 +1,427 @@
+// Plan construction on the GPU: Legendre / Wigner blocks (Sec. III-F/G),
+// per-order inversion of P_m by Newton-Schulz iteration, and the stacked
+// forward operators Q_m = [P_m^{-1}; A_m^top P_m^{-1}].
+//
+// Block A_m (slot layout, column-major, rows = rings k = 0..L-1, columns =
+// degrees l = l0..L-1):  A_m[k, i] = sY_{l0+i}^m(theta_k, 0).
+// P_m = rows k >= |m| of A_m (Eq. Y_matrix without the common 2 pi), the
+// "top" rows k < |m| evaluate order m on the rings where it aliases
+// (Eq. signal_subset).  Forward operator per slot:
+//     Q_m = [ X_m ; A_m^top X_m ],  X_m = P_m^{-1} (P_m^+ when |m| < |s|)
+// so that one product Q_m g_m yields the order-m coefficients and the
+// values G'_m(theta_k) on the rings k < |m| that later orders subtract.
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "common.hpp"
+#include "host_util.hpp"
+
+namespace osht {
+
+namespace {
+
+constexpr double kBig = 0x1p256, kSmall = 0x1p-256;
+
+// ---------------------------------------------------------------- Legendre
+// Spin 0, slot am, ring k: upward recurrence in l from the seed
+// Pt[am, am] = prod_{i=1..am} (-sqrt((2i+1)/(2i)) sin theta) / sqrt(4 pi),
+// with values carried as mantissa * 2^e while below the double range.
+__global__ __launch_bounds__(256) void legendre_s0_kernel(int L, const double* __restrict__ cs,
+                                                          const double* __restrict__ sn, const Slot* __restrict__ slots,
+                                                          double* __restrict__ A) {
+  const int am = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= L) return;
+  const Slot sl = slots[am];
+  double* out = A + sl.offA + k;
+  const double x = cs[k], y = sn[k];
+  double p = 0.28209479177387814347;  // 1/sqrt(4 pi)
+  int e = 0;
+  for (int i = 1; i <= am && p != 0.0; ++i) {
+    p *= -sqrt((2.0 * i + 1.0) / (2.0 * i)) * y;
+    if (fabs(p) < kSmall && p != 0.0) {
+      int de;
+      p = frexp(p, &de);
+      e += de;
+    }
+  }
+  double prev = 0.0, cur = p;
+  out[0] = ldexp(cur, e);
+  for (int l = am; l < L - 1; ++l) {
+    const double den = (double)(l + 1) * (l + 1) - (double)am * am;
+    const double a = sqrt((2.0 * l + 1.0) * (2.0 * l + 3.0) / den);
+    const double b = (l == am) ? 0.0 : sqrt((2.0 * l + 3.0) * ((double)l * l - (double)am * am) / ((2.0 * l - 1.0) * den));
+    const double nxt = a * x * cur - b * prev;
+    prev = cur;
+    cur = nxt;
+    const double mag = fmax(fabs(prev), fabs(cur));
+    if (mag > kBig) { prev *= kSmall; cur *= kSmall; e += 256; }
+    else if (mag < kSmall && mag > 0.0) { prev *= kBig; cur *= kBig; e -= 256; }
+    out[(int64_t)(l + 1 - am) * sl.ldA] = ldexp(cur, e);
+  }
+}
+
+// Spin s, slot for signed order m, ring k:
+// sY_l^m(theta, 0) = (-1)^s sqrt((2l+1)/(4 pi)) d^l_{m,-s}(theta), with the
+// Wigner-d recurrence in l for fixed (a, b) = (m, -s) started at
+// j = max(|a|, |b|) from the single surviving term of Wigner's sum:
+//   d^j_{ab} = sign * sqrt(C(2j, j+c)) cos^p(theta/2) sin^q(theta/2).
+__global__ __launch_bounds__(256) void legendre_spin_kernel(int L, int s, const double* __restrict__ cs,
+                                                            const double* __restrict__ ch, const double* __restrict__ sh,
+                                                            const Slot* __restrict__ slots, double* __restrict__ A) {
+  const int slot = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= L) return;
+  const Slot sl = slots[slot];
+  const int a = sl.m, b = -s;
+  const int j0 = sl.l0;
+  double* out = A + sl.offA + k;
+  int sign, pc, ps, c;
+  if (abs(a) >= abs(b)) {
+    c = b;
+    if (a == j0) { sign = ((j0 - b) & 1) ? -1 : 1; pc = j0 + b; ps = j0 - b; }
+    else { sign = 1; pc = j0 - b; ps = j0 + b; }
+  } else {
+    c = a;
+    if (b == j0) { sign = 1; pc = j0 + a; ps = j0 - a; }
+    else { sign = ((j0 + a) & 1) ? -1 : 1; pc = j0 - a; ps = j0 + a; }
+  }
+  // C(2j, j+c) = prod_{i=1}^{j-c} (j+c+i)/i, taken under a square root
+  double p = (double)sign;
+  int e = 0;
+  auto renorm = [&]() {
+    if (p != 0.0 && (fabs(p) < kSmall || fabs(p) > kBig)) {
+      int de;
+      p = frexp(p, &de);
+      e += de;
+    }
+  };
+  for (int i = 1; i <= j0 - c; ++i) { p *= sqrt((double)(j0 + c + i) / (double)i); renorm(); }
+  const double cv = ch[k], sv = sh[k];
+  for (int i = 0; i < pc && p != 0.0; ++i) { p *= cv; renorm(); }
+  for (int i = 0; i < ps && p != 0.0; ++i) { p *= sv; renorm(); }
+  const double sgn_s = (s & 1) ? -1.0 : 1.0;
+  const double inv4pi = 0.07957747154594766788;  // 1/(4 pi)
+  double prev = 0.0, cur = p;
+  out[0] = sgn_s * sqrt((2.0 * j0 + 1.0) * inv4pi) * ldexp(cur, e);
+  const double x = cs[k];
+  for (int j = j0; j < L - 1; ++j) {
+    double nxt;
+    if (j == 0) {
+      nxt = x * cur;
+    } else {
+      const double dn = (double)j * sqrt(((double)(j + 1) * (j + 1) - (double)a * a) * ((double)(j + 1) * (j + 1) - (double)b * b));
+      const double c1 = (2.0 * j + 1.0) * ((double)j * (j + 1) * x - (double)a * b);
+      const double c2 = (double)(j + 1) * sqrt(((double)j * j - (double)a * a) * ((double)j * j - (double)b * b));
+      nxt = (c1 * cur - c2 * prev) / dn;
+    }
+    prev = cur;
+    cur = nxt;
+    const double mag = fmax(fabs(prev), fabs(cur));
+    if (mag > kBig) { prev *= kSmall; cur *= kSmall; e += 256; }
+    else if (mag < kSmall && mag > 0.0) { prev *= kBig; cur *= kBig; e -= 256; }
+    const int l = j + 1;
+    out[(int64_t)(l - j0) * sl.ldA] = sgn_s * sqrt((2.0 * l + 1.0) * inv4pi) * ldexp(cur, e);
+  }
+}
+
+// ---------------------------------------------------------------- Newton-Schulz
+// Per slot: ||P||_1 ||P||_inf, P = rows |m|.. of A (R x K).
+__global__ __launch_bounds__(256) void pnorms_kernel(const Slot* __restrict__ slots, int slot0, const double* __restrict__ A,
+                                                     double* __restrict__ out) {
+  const Slot sl = slots[slot0 + blockIdx.x];
+  const int am = sl.m < 0 ? -sl.m : sl.m;
+  const double* P = A + sl.offA + am;
+  __shared__ double red[2][256];
+  double cmax = 0.0, rmax = 0.0;
+  for (int j = threadIdx.x; j < sl.K; j += blockDim.x) {  // column sums
+    double acc = 0.0;
+    for (int i = 0; i < sl.R; ++i) acc += fabs(P[(int64_t)j * sl.ldA + i]);
+    cmax = fmax(cmax, acc);
+  }
+  for (int i = threadIdx.x; i < sl.R; i += blockDim.x) {  // row sums
+    double acc = 0.0;
+    for (int j = 0; j < sl.K; ++j) acc += fabs(P[(int64_t)j * sl.ldA + i]);
+    rmax = fmax(rmax, acc);
+  }
+  red[0][threadIdx.x] = cmax;
+  red[1][threadIdx.x] = rmax;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = red[0][0];
+    out[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+// X0 = alpha P^T into the top K rows of Q (K x R, column-major, ld ldQ).
+__global__ __launch_bounds__(256) void ns_init_kernel(const Slot* __restrict__ slots, int slot0, const double* __restrict__ A,
+                                                      double* __restrict__ Q, const double* __restrict__ norms) {
+  const Slot sl = slots[slot0 + blockIdx.y];
+  const int am = sl.m < 0 ? -sl.m : sl.m;
+  const double alpha = 1.0 / (norms[2 * blockIdx.y] * norms[2 * blockIdx.y + 1]);
+  const int64_t total = (int64_t)sl.K * sl.R;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % sl.K), j = (int)(e / sl.K);  // X[i][j] = alpha P[j][i]
+    Q[sl.offQ + (int64_t)j * sl.ldQ + i] = alpha * A[sl.offA + (int64_t)i * sl.ldA + am + j];
+  }
+}
+
+// Y = scale * X for a K x R block per slot: X at Q top (ld ldQ) or at a
+// packed scratch block (ld K); direction chosen by `to_q`.
+__global__ __launch_bounds__(256) void ns_copy_kernel(const Slot* __restrict__ slots, int slot0, double* __restrict__ Q,
+                                                      double* __restrict__ scr, const int64_t* __restrict__ offXn,
+                                                      double scale, int to_q) {
+  const Slot sl = slots[slot0 + blockIdx.y];
+  const int64_t total = (int64_t)sl.K * sl.R;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % sl.K), j = (int)(e / sl.K);
+    double* q = Q + sl.offQ + (int64_t)j * sl.ldQ + i;
+    double* x = scr + offXn[blockIdx.y] + e;
+    if (to_q) *q = scale * (*x); else *x = scale * (*q);
+  }
+}
+
+// max_ij |E_ij - delta_ij| for E = X P (K x K packed, ld K) per slot.
+__global__ __launch_bounds__(256) void ns_resid_kernel(const Slot* __restrict__ slots, int slot0, const double* __restrict__ scr,
+                                                       const int64_t* __restrict__ offE, double* __restrict__ out) {
+  const Slot sl = slots[slot0 + blockIdx.x];
+  const double* E = scr + offE[blockIdx.x];
+  const int64_t total = (int64_t)sl.K * sl.K;
+  double mx = 0.0;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int i = (int)(e % sl.K), j = (int)(e / sl.K);
+    const double v = E[e] - (i == j ? 1.0 : 0.0);
+    mx = fmax(mx, (v != v) ? INFINITY : fabs(v));
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// ||X||_1 (max column abs sum of the K x R block at Q top) per slot.
+__global__ __launch_bounds__(256) void xnorm1_kernel(const Slot* __restrict__ slots, int slot0, const double* __restrict__ Q,
+                                                     double* __restrict__ out) {
+  const Slot sl = slots[slot0 + blockIdx.x];
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < sl.R; j += blockDim.x) {
+    double acc = 0.0;
+    for (int i = 0; i < sl.K; ++i) acc += fabs(Q[sl.offQ + (int64_t)j * sl.ldQ + i]);
+    mx = fmax(mx, acc);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+template <class T>
+void put(DevBuf& d, const std::vector<T>& h) {
+  d.reserve(h.size() * sizeof(T));
+  if (!h.empty()) OSHT_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// Newton-Schulz for the slots [s0, s1): X <- 2X - X (P X), started from
+// X0 = P^T / (||P||_1 ||P||_inf); stops when max |X P - I| no longer
+// improves.  Leaves X_m in the top K rows of Q_m; returns the final residual
+// and the 1-norm condition estimates via kappa_out.
+double newton_schulz(Plan& p, int s0, int s1, DevBuf& scratch, std::vector<double>& kappa_out) {
+  const int ns = s1 - s0;
+  const Slot* d_slots = p.d_slots.as<Slot>();
+  double* A = p.d_A.as<double>();
+  double* Q = p.d_Q.as<double>();
+  std::vector<int64_t> offT(ns), offXn(ns), offE(ns);
+  int64_t tot = 0;
+  for (int i = 0; i < ns; ++i) {
+    const Slot& sl = p.slots[s0 + i];
+    offT[i] = tot; tot += (int64_t)sl.R * sl.R;
+    offXn[i] = tot; tot += (int64_t)sl.K * sl.R;
+    offE[i] = tot; tot += (int64_t)sl.K * sl.K;
+  }
+  scratch.reserve(tot * sizeof(double));
+  double* scr = scratch.as<double>();
+  DevBuf d_offXn, d_offE, d_norms, d_out;
+  upload(d_offXn, offXn);
+  upload(d_offE, offE);
+  d_norms.alloc(sizeof(double) * 2 * ns);
+  d_out.alloc(sizeof(double) * ns);
+  std::vector<GemmDesc> dPX(ns), dXT(ns), dXP(ns);
+  for (int i = 0; i < ns; ++i) {
+    const Slot& sl = p.slots[s0 + i];
+    const int am = std::abs(sl.m);
+    const double* P = A + sl.offA + am;
+    double* X = Q + sl.offQ;
+    double* T = scr + offT[i];
+    double* Xn = scr + offXn[i];
+    double* E = scr + offE[i];
+    dPX[i] = GemmDesc{P, X, T, 1, sl.ldA, 1, sl.ldQ, 1, sl.R, sl.R, sl.R, sl.K, 0, 1.0, 0.0};
+    dXT[i] = GemmDesc{X, T, Xn, 1, sl.ldQ, 1, sl.R, 1, sl.K, sl.K, sl.R, sl.R, 0, -1.0, 1.0};
+    dXP[i] = GemmDesc{X, P, E, 1, sl.ldQ, 1, sl.ldA, 1, sl.K, sl.K, sl.K, sl.R, 0, 1.0, 0.0};
+  }
+  std::vector<GemmTask> tPX, tXT, tXP;
+  gemm_tasks(dPX, tPX);
+  gemm_tasks(dXT, tXT);
+  gemm_tasks(dXP, tXP);
+  DevBuf gPX, gXT, gXP, kPX, kXT, kXP;
+  upload(gPX, dPX); upload(gXT, dXT); upload(gXP, dXP);
+  upload(kPX, tPX); upload(kXT, tXT); upload(kXP, tXP);
+  hipLaunchKernelGGL(pnorms_kernel, dim3(ns), dim3(256), 0, 0, d_slots, s0, A, d_norms.as<double>());
+  OSHT_HIP(hipGetLastError());
+  std::vector<double> norms(2 * ns);
+  OSHT_HIP(hipMemcpy(norms.data(), d_norms.p, sizeof(double) * 2 * ns, hipMemcpyDeviceToHost));
+  hipLaunchKernelGGL(ns_init_kernel, dim3(64, ns), dim3(256), 0, 0, d_slots, s0, A, Q, d_norms.as<double>());
+  OSHT_HIP(hipGetLastError());
+  std::vector<double> res(ns);
+  double best = INFINITY, last = INFINITY;
+  int stall = 0;
+  for (int it = 0; it < 120; ++it) {
+    launch_gemm_f64(gPX.as<GemmDesc>(), kPX.as<GemmTask>(), (int)tPX.size(), 0);
+    hipLaunchKernelGGL(ns_copy_kernel, dim3(64, ns), dim3(256), 0, 0, d_slots, s0, Q, scr, d_offXn.as<int64_t>(), 2.0, 0);
+    launch_gemm_f64(gXT.as<GemmDesc>(), kXT.as<GemmTask>(), (int)tXT.size(), 0);
+    hipLaunchKernelGGL(ns_copy_kernel, dim3(64, ns), dim3(256), 0, 0, d_slots, s0, Q, scr, d_offXn.as<int64_t>(), 1.0, 1);
+    OSHT_HIP(hipGetLastError());
+    if (it < 8) continue;
+    launch_gemm_f64(gXP.as<GemmDesc>(), kXP.as<GemmTask>(), (int)tXP.size(), 0);
+    hipLaunchKernelGGL(ns_resid_kernel, dim3(ns), dim3(256), 0, 0, d_slots, s0, scr, d_offE.as<int64_t>(), d_out.as<double>());
+    OSHT_HIP(hipGetLastError());
+    OSHT_HIP(hipMemcpy(res.data(), d_out.p, sizeof(double) * ns, hipMemcpyDeviceToHost));
+    double mx = 0.0;
+    for (double r : res) mx = std::max(mx, r);
+    if (!(mx == mx)) mx = INFINITY;
+    best = std::min(best, mx);
+    if (mx < 1e-15) break;
+    // quadratic phase has ended once the residual stops halving
+    if (mx < 1e-3 && mx > 0.5 * last) { if (++stall >= 2) break; } else stall = 0;
+    last = mx;
+  }
+  hipLaunchKernelGGL(xnorm1_kernel, dim3(ns), dim3(256), 0, 0, d_slots, s0, Q, d_out.as<double>());
+  OSHT_HIP(hipGetLastError());
+  std::vector<double> xn(ns);
+  OSHT_HIP(hipMemcpy(xn.data(), d_out.p, sizeof(double) * ns, hipMemcpyDeviceToHost));
+  for (int i = 0; i < ns; ++i) kappa_out.push_back(norms[2 * i] * xn[i]);
+  return best;
+}
+
+}  // namespace
+
+int64_t Plan::device_bytes() const {
+  return (int64_t)(d_cos.bytes + d_sin.bytes + d_cosh.bytes + d_sinh.bytes + d_slots.bytes + d_A.bytes + d_Q.bytes +
+                   d_rings.bytes + d_chirp.bytes + d_twiddle.bytes + w_X.bytes + w_Y.bytes + w_H.bytes + w_T.bytes +
+                   d_gdesc.bytes + d_gtask.bytes);
+}
+
+void build_plan(Plan& p) {
+  const int L = p.L, s = p.spin;
+  // ring trigonometry
+  std::vector<double> cs(L), sn(L), chv(L), shv(L);
+  for (int k = 0; k < L; ++k) ring_trig(L, p.numer[k], &cs[k], &sn[k], &chv[k], &shv[k]);
+  upload(p.d_cos, cs);
+  upload(p.d_sin, sn);
+  upload(p.d_cosh, chv);
+  upload(p.d_sinh, shv);
+  // slots
+  p.slots.clear();
+  const int ldA = round_up(L, 8);
+  int64_t offA = 0, offQ = 0;
+  auto add_slot = [&](int m) {
+    Slot sl{};
+    sl.m = m;
+    sl.l0 = std::max(std::abs(m), std::abs(s));
+    sl.K = L - sl.l0;
+    sl.R = L - std::abs(m);
+    sl.ldA = ldA;
+    sl.offA = offA;
+    offA += (int64_t)ldA * sl.K;
+    sl.ldQ = round_up(sl.K + std::abs(m), 8);
+    sl.offQ = offQ;
+    offQ += (int64_t)sl.ldQ * sl.R;
+    p.slots.push_back(sl);
+  };
+  if (s == 0) {
+    for (int am = 0; am < L; ++am) add_slot(am);
+    p.ncols_per_map = 4;
+  } else {
+    for (int m = -(L - 1); m <= L - 1; ++m) add_slot(m);
+    p.ncols_per_map = 2;
+  }
+  p.nslots = (int)p.slots.size();
+  upload(p.d_slots, p.slots);
+  p.d_A.alloc(sizeof(double) * offA);
+  p.d_Q.alloc(sizeof(double) * offQ);
+  OSHT_HIP(hipMemset(p.d_A.p, 0, p.d_A.bytes));
+  OSHT_HIP(hipMemset(p.d_Q.p, 0, p.d_Q.bytes));
+  // Legendre / Wigner blocks
+  const dim3 grid((unsigned)ceil_div(L, 256), (unsigned)p.nslots);
+  if (s == 0) {
+    hipLaunchKernelGGL(legendre_s0_kernel, grid, dim3(256), 0, 0, L, p.d_cos.as<double>(), p.d_sin.as<double>(),
+                       p.d_slots.as<Slot>(), p.d_A.as<double>());
+  } else {
+    hipLaunchKernelGGL(legendre_spin_kernel, grid, dim3(256), 0, 0, L, s, p.d_cos.as<double>(), p.d_cosh.as<double>(),
+                       p.d_sinh.as<double>(), p.d_slots.as<Slot>(), p.d_A.as<double>());
+  }
+  OSHT_HIP(hipGetLastError());
+  // Newton-Schulz inverses, in chunks bounded by a scratch budget
+  DevBuf scratch;
+  const int64_t budget = (int64_t)1 << 28;  // doubles (2 GiB)
+  std::vector<double> kap;
+  p.max_resid = 0.0;
+  for (int s0 = 0; s0 < p.nslots;) {
+    int64_t need = 0;
+    int s1 = s0;
+    while (s1 < p.nslots) {
+      const Slot& sl = p.slots[s1];
+      const int64_t n1 = (int64_t)sl.R * sl.R + (int64_t)sl.K * sl.R + (int64_t)sl.K * sl.K;
+      if (s1 > s0 && need + n1 > budget) break;
+      need += n1;
+      ++s1;
+    }
+    p.max_resid = std::max(p.max_resid, newton_schulz(p, s0, s1, scratch, kap));
+    s0 = s1;
+  }
+  scratch.release();
+  p.max_kappa = 0.0;
+  for (double k : kap) p.max_kappa = std::max(p.max_kappa, k);
+  OSHT_CHECK(p.max_resid < 1e-6, OSHT_ESINGULAR,
+             "per-order inversion did not converge (max |X P - I| = " + std::to_string(p.max_resid) + ")");
+  // bottom rows of Q: A^top X
+  std::vector<GemmDesc> dC;
+  for (int i = 0; i < p.nslots; ++i) {
+    const Slot& sl = p.slots[i];
+    const int am = std::abs(sl.m);
+    if (am == 0) continue;
+    const double* At = p.d_A.as<double>() + sl.offA;
+    const double* X = p.d_Q.as<double>() + sl.offQ;
+    double* C = p.d_Q.as<double>() + sl.offQ + sl.K;
+    dC.push_back(GemmDesc{At, X, C, 1, sl.ldA, 1, sl.ldQ, 1, sl.ldQ, am, sl.R, sl.K, 0, 1.0, 0.0});
+  }
+  if (!dC.empty()) {
+    std::vector<GemmTask> tC;
+    gemm_tasks(dC, tC);
+    DevBuf gd, gt;
+    upload(gd, dC);
+    upload(gt, tC);
+    launch_gemm_f64(gd.as<GemmDesc>(), gt.as<GemmTask>(), (int)tC.size(), 0);
+    OSHT_HIP(hipDeviceSynchronize());
+  }
+  build_chirps(p);
+  OSHT_HIP(hipDeviceSynchronize());
+}
+
+}  // namespace osht

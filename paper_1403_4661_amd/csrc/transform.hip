@@ -1,0 +1,367 @@
+// The four transforms: inverse (Procedure 2), forward (Procedure 1) and
+// their adjoints, as sequences of gather / order-wise GEMM / scatter / ring
+// DFT kernels on one stream.
+//
+// Internal per-call buffers (doubles, map-fastest so that GEMM operands are
+// contiguous):
+//   X[slot][row][col], Y[slot][row][col]  row < L, col < ncols
+//   H[(k^2 + q) * B + b]                   ring bins (complex)
+// Column col of a slot encodes (sign, map, re/im): spin 0 uses
+// col = sgn * 2B + 2b + part for the orders +am (sgn 0) and -am (sgn 1);
+// spin s != 0 uses col = 2b + part for the slot's single order.
+//
+// Inverse:  X_m = coefficients of order m (rows l = l0..L-1)
+//           Y_m = A_m X_m : G'_m(theta_k) on every ring k
+//           f   = per ring, fold order m into bin (m mod n_k), inverse DFT.
+// Forward (descending |m|):
+//           X_m[k - |m|] = H_k[m mod n_k] - sum_{m' = m mod n_k, |m'| > k} G'_{m'}(theta_k)
+//           Y_m = Q_m X_m = [ f_m ; G'_m(theta_k), k < |m| ]
+// The aliases G'_{m'}(theta_k) of the already-solved orders are read back
+// from the Y blocks of those orders (their bottom |m'| rows), so no bin is
+// ever updated in place and every sum is taken in a fixed order.
+// Spin 0: P_{-m} = (-1)^m P_m, hence Q_{-m} = [(-1)^m P_m^{-1}; A^top_m P_m^{-1}]
+// and A_{-m} = (-1)^m A_m; the sign is applied where coefficients enter or
+// leave the slot buffers.
+
+#include "common.hpp"
+
+namespace osht {
+
+void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, const double* Y, double* f, int64_t B,
+                           hipStream_t st);
+
+namespace {
+
+struct Geo {
+  int L, s, B, ncols;
+};
+
+__device__ __forceinline__ int pmod(int a, int n) {
+  const int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+// decode a slot column into (sgn, map, part) and the signed order
+__device__ __forceinline__ void decode_col(const Geo& g, const Slot& sl, int col, int& sgn, int& b, int& part, int& m) {
+  if (g.s == 0) {
+    sgn = col / (2 * g.B);
+    const int r = col - sgn * 2 * g.B;
+    b = r >> 1;
+    part = r & 1;
+    m = sgn ? -sl.m : sl.m;
+  } else {
+    sgn = 0;
+    b = col >> 1;
+    part = col & 1;
+    m = sl.m;
+  }
+}
+
+// Y-buffer location of G'_{m'}(theta_k) for the forward pass (the bottom
+// rows of the slot of order m'), for map b / part.
+__device__ __forceinline__ int64_t alias_index(const Geo& g, const Slot* __restrict__ slots, int mp, int k, int b, int part) {
+  int slot, col;
+  if (g.s == 0) {
+    slot = mp < 0 ? -mp : mp;
+    col = (mp < 0 ? 2 * g.B : 0) + 2 * b + part;
+  } else {
+    slot = mp + g.L - 1;
+    col = 2 * b + part;
+  }
+  const int K = slots[slot].K;
+  return ((int64_t)slot * g.L + K + k) * g.ncols + col;
+}
+
+// Inverse: X[slot][i][col] = coefficient (l0+i, m) of map b (sign-adjusted).
+__global__ __launch_bounds__(256) void inv_gather_kernel(Geo g, const Slot* __restrict__ slots, int slot0,
+                                                         const double* __restrict__ flm, double* __restrict__ X) {
+  const int slot = slot0 + blockIdx.y;
+  const Slot sl = slots[slot];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = e / g.ncols, col = e % g.ncols;
+  if (i >= sl.K) return;
+  int sgn, b, part, m;
+  decode_col(g, sl, col, sgn, b, part, m);
+  const int l = sl.l0 + i;
+  double v = flm[((int64_t)b * g.L * g.L + (int64_t)l * l + l + m) * 2 + part];
+  if (g.s == 0 && sgn && (sl.m & 1)) v = -v;
+  X[((int64_t)slot * g.L + i) * g.ncols + col] = v;
+}
+
+// Forward, one level: X[slot][r][col], ring k = |m| + r: bin minus aliases.
+__global__ __launch_bounds__(256) void fwd_gather_kernel(Geo g, const Slot* __restrict__ slots, int slot0,
+                                                         const double* __restrict__ H, const double* __restrict__ Y,
+                                                         double* __restrict__ X) {
+  const int slot = slot0 + blockIdx.y;
+  const Slot sl = slots[slot];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = e / g.ncols, col = e % g.ncols;
+  if (r >= sl.R) return;
+  int sgn, b, part, m;
+  decode_col(g, sl, col, sgn, b, part, m);
+  const int am = m < 0 ? -m : m;
+  const int k = am + r, n = 2 * k + 1;
+  const int bin = pmod(m, n);
+  double v = H[(((int64_t)k * k + bin) * g.B + b) * 2 + part];
+  const int start = bin - ((bin + g.L - 1) / n) * n;  // smallest m' >= -(L-1), m' = m (mod n)
+  for (int mp = start; mp <= g.L - 1; mp += n) {
+    if (mp == m) continue;
+    v -= Y[alias_index(g, slots, mp, k, b, part)];
+  }
+  X[((int64_t)slot * g.L + r) * g.ncols + col] = v;
+}
+
+// Forward: flm[b][l^2 + l + m] from the coefficient rows of Y (pull form;
+// zeros for l < |s|).
+__global__ __launch_bounds__(256) void fwd_scatter_kernel(Geo g, const Slot* __restrict__ slots,
+                                                          const double* __restrict__ Y, double* __restrict__ flm,
+                                                          double sign_neg) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t LL = (int64_t)g.L * g.L;
+  if (e >= LL * g.B) return;
+  const int b = (int)(e / LL);
+  const int idx = (int)(e - (int64_t)b * LL);
+  const int l = (int)sqrt((double)idx);
+  int ll = l;
+  while ((int64_t)(ll + 1) * (ll + 1) <= idx) ++ll;
+  while ((int64_t)ll * ll > idx) --ll;
+  const int m = idx - ll * ll - ll;
+  double re = 0.0, im = 0.0;
+  int slot, col;
+  if (g.s == 0) {
+    slot = m < 0 ? -m : m;
+    col = (m < 0 ? 2 * g.B : 0) + 2 * b;
+  } else {
+    slot = m + g.L - 1;
+    col = 2 * b;
+  }
+  const Slot sl = slots[slot];
+  if (ll >= sl.l0) {
+    const double* y = Y + ((int64_t)slot * g.L + (ll - sl.l0)) * g.ncols + col;
+    re = y[0];
+    im = y[1];
+    if (g.s == 0 && m < 0 && (slot & 1)) { re *= sign_neg; im *= sign_neg; }
+  }
+  flm[e * 2] = re;
+  flm[e * 2 + 1] = im;
+}
+
+// Inverse adjoint: X[slot][k][col] = Hbar_k[m mod n_k] for every ring k.
+__global__ __launch_bounds__(256) void iadj_gather_kernel(Geo g, const Slot* __restrict__ slots, int slot0,
+                                                          const double* __restrict__ H, double* __restrict__ X) {
+  const int slot = slot0 + blockIdx.y;
+  const Slot sl = slots[slot];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = e / g.ncols, col = e % g.ncols;
+  if (k >= g.L) return;
+  int sgn, b, part, m;
+  decode_col(g, sl, col, sgn, b, part, m);
+  const int n = 2 * k + 1;
+  X[((int64_t)slot * g.L + k) * g.ncols + col] = H[(((int64_t)k * k + pmod(m, n)) * g.B + b) * 2 + part];
+}
+
+// Forward adjoint, one level: X[slot][i][col] = [ ybar (i < K) ; -Hbar_k[m mod n_k] (k = i - K < |m|) ].
+__global__ __launch_bounds__(256) void fadj_gather_kernel(Geo g, const Slot* __restrict__ slots, int slot0,
+                                                          const double* __restrict__ flmbar, const double* __restrict__ H,
+                                                          double* __restrict__ X) {
+  const int slot = slot0 + blockIdx.y;
+  const Slot sl = slots[slot];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = e / g.ncols, col = e % g.ncols;
+  int sgn, b, part, m;
+  decode_col(g, sl, col, sgn, b, part, m);
+  const int am = m < 0 ? -m : m;
+  if (i >= sl.K + am) return;
+  double v;
+  if (i < sl.K) {
+    const int l = sl.l0 + i;
+    v = flmbar[((int64_t)b * g.L * g.L + (int64_t)l * l + l + m) * 2 + part];
+    if (g.s == 0 && sgn && (am & 1)) v = -v;
+  } else {
+    const int k = i - sl.K, n = 2 * k + 1;
+    v = -H[(((int64_t)k * k + pmod(m, n)) * g.B + b) * 2 + part];
+  }
+  X[((int64_t)slot * g.L + i) * g.ncols + col] = v;
+}
+
+// Forward adjoint, one level: Hbar_k[m mod n_k] = Y[slot][k - |m|][col], k >= |m|.
+__global__ __launch_bounds__(256) void fadj_scatter_kernel(Geo g, const Slot* __restrict__ slots, int slot0,
+                                                           const double* __restrict__ Y, double* __restrict__ H) {
+  const int slot = slot0 + blockIdx.y;
+  const Slot sl = slots[slot];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = e / g.ncols, col = e % g.ncols;
+  if (r >= sl.R) return;
+  int sgn, b, part, m;
+  decode_col(g, sl, col, sgn, b, part, m);
+  if (g.s == 0 && sgn && sl.m == 0) return;  // -0 duplicates +0
+  const int am = m < 0 ? -m : m;
+  const int k = am + r, n = 2 * k + 1;
+  H[(((int64_t)k * k + pmod(m, n)) * g.B + b) * 2 + part] = Y[((int64_t)slot * g.L + r) * g.ncols + col];
+}
+
+// Inverse adjoint: flmbar from the K rows of Y (pull form; zeros for l < |s|).
+// Same addressing as fwd_scatter_kernel.
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+namespace {
+
+enum { kInv = 0, kFwd = 1, kIadj = 2, kFadj = 3 };
+
+void ensure_workspace(Plan& p, int64_t B) {
+  const int64_t ncols = p.ncols_per_map * B;
+  const size_t xy = sizeof(double) * (size_t)p.nslots * p.L * ncols;
+  const size_t hb = sizeof(double) * 2 * (size_t)p.L * p.L * B;
+  const bool grow = (xy > p.w_X.bytes) || (hb > p.w_H.bytes);
+  p.w_X.reserve(xy);
+  p.w_Y.reserve(xy);
+  p.w_H.reserve(hb);
+  if (!grow && p.ws_batch == B && !p.h_gdesc.empty()) return;
+  // GEMM descriptors for the four directions, one per slot each
+  p.h_gdesc.clear();
+  double* X = p.w_X.as<double>();
+  double* Y = p.w_Y.as<double>();
+  const double* A = p.d_A.as<double>();
+  const double* Q = p.d_Q.as<double>();
+  for (int dir = 0; dir < 4; ++dir) {
+    for (int i = 0; i < p.nslots; ++i) {
+      const Slot& sl = p.slots[i];
+      const int am = std::abs(sl.m);
+      double* Xs = X + (int64_t)i * p.L * ncols;
+      double* Ys = Y + (int64_t)i * p.L * ncols;
+      GemmDesc d{};
+      d.B = Xs; d.sBr = ncols; d.sBc = 1;
+      d.C = Ys; d.sCr = ncols; d.sCc = 1;
+      d.N = (int)ncols; d.alpha = 1.0; d.beta = 0.0;
+      if (dir == kInv) { d.A = A + sl.offA; d.sAr = 1; d.sAc = sl.ldA; d.M = p.L; d.K = sl.K; }
+      if (dir == kFwd) { d.A = Q + sl.offQ; d.sAr = 1; d.sAc = sl.ldQ; d.M = sl.K + am; d.K = sl.R; }
+      if (dir == kIadj) { d.A = A + sl.offA; d.sAr = sl.ldA; d.sAc = 1; d.M = sl.K; d.K = p.L; }
+      if (dir == kFadj) { d.A = Q + sl.offQ; d.sAr = sl.ldQ; d.sAc = 1; d.M = sl.R; d.K = sl.K + am; }
+      p.h_gdesc.push_back(d);
+    }
+  }
+  gemm_tasks(p.h_gdesc, p.h_gtask);
+  upload(p.d_gdesc, p.h_gdesc);
+  upload(p.d_gtask, p.h_gtask);
+  p.ws_batch = B;
+}
+
+// task range [first, count) of the GEMMs for direction dir, slots [s0, s1)
+void task_range(const Plan& p, int dir, int s0, int s1, int& first, int& count) {
+  const int d0 = dir * p.nslots + s0, d1 = dir * p.nslots + s1;
+  // tasks are emitted in descriptor order
+  int lo = 0, hi = (int)p.h_gtask.size();
+  {
+    int a = 0, b = hi;
+    while (a < b) { int mid = (a + b) / 2; if (p.h_gtask[mid].desc < d0) a = mid + 1; else b = mid; }
+    lo = a;
+  }
+  {
+    int a = lo, b = hi;
+    while (a < b) { int mid = (a + b) / 2; if (p.h_gtask[mid].desc < d1) a = mid + 1; else b = mid; }
+    hi = a;
+  }
+  first = lo;
+  count = hi - lo;
+}
+
+void gemm_slots(const Plan& p, int dir, int s0, int s1, hipStream_t st) {
+  int first, count;
+  task_range(p, dir, s0, s1, first, count);
+  launch_gemm_f64(p.d_gdesc.as<GemmDesc>(), p.d_gtask.as<GemmTask>() + first, count, st);
+}
+
+Geo geo(const Plan& p, int64_t B) { return Geo{p.L, p.spin, (int)B, (int)(p.ncols_per_map * B)}; }
+
+// slots of level am: spin 0 -> [am, am+1); spin s -> {-am, +am}
+void level_slots(const Plan& p, int am, int& s0, int& s1) {
+  if (p.spin == 0) { s0 = am; s1 = am + 1; return; }
+  const int c = p.L - 1;
+  if (am == 0) { s0 = c; s1 = c + 1; return; }
+  s0 = c - am; s1 = c + am + 1;  // contains the two slots at the ends only
+}
+
+}  // namespace
+
+void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t st) {
+  ensure_workspace(p, B);
+  const Geo g = geo(p, B);
+  const dim3 grid((unsigned)ceil_div((int64_t)p.L * g.ncols, 256), (unsigned)p.nslots);
+  hipLaunchKernelGGL(inv_gather_kernel, grid, dim3(256), 0, st, g, p.d_slots.as<Slot>(), 0, flm, p.w_X.as<double>());
+  OSHT_HIP(hipGetLastError());
+  gemm_slots(p, kInv, 0, p.nslots, st);
+  launch_ring_synthesis(p, nullptr, 0, p.w_Y.as<double>(), f, B, st);
+}
+
+void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {
+  ensure_workspace(p, B);
+  const Geo g = geo(p, B);
+  launch_ring_analysis(p, f, p.w_H.as<double>(), B, true, st);
+  const dim3 blk(256);
+  for (int am = p.L - 1; am >= 0; --am) {
+    int s0, s1;
+    level_slots(p, am, s0, s1);
+    const int R = p.L - am;
+    const unsigned gx = (unsigned)ceil_div((int64_t)R * g.ncols, 256);
+    if (p.spin == 0 || am == 0) {
+      hipLaunchKernelGGL(fwd_gather_kernel, dim3(gx, s1 - s0), blk, 0, st, g, p.d_slots.as<Slot>(), s0,
+                         p.w_H.as<double>(), p.w_Y.as<double>(), p.w_X.as<double>());
+      OSHT_HIP(hipGetLastError());
+      gemm_slots(p, kFwd, s0, s1, st);
+    } else {
+      for (int sl : {s0, s1 - 1}) {
+        hipLaunchKernelGGL(fwd_gather_kernel, dim3(gx, 1), blk, 0, st, g, p.d_slots.as<Slot>(), sl,
+                           p.w_H.as<double>(), p.w_Y.as<double>(), p.w_X.as<double>());
+        OSHT_HIP(hipGetLastError());
+        gemm_slots(p, kFwd, sl, sl + 1, st);
+      }
+    }
+  }
+  const int64_t tot = (int64_t)p.L * p.L * B;
+  hipLaunchKernelGGL(fwd_scatter_kernel, dim3((unsigned)ceil_div(tot, 256)), blk, 0, st, g, p.d_slots.as<Slot>(),
+                     p.w_Y.as<double>(), flm, -1.0);
+  OSHT_HIP(hipGetLastError());
+}
+
+void run_inverse_adjoint(Plan& p, const double* fbar, double* flmbar, int64_t B, hipStream_t st) {
+  ensure_workspace(p, B);
+  const Geo g = geo(p, B);
+  launch_ring_analysis(p, fbar, p.w_H.as<double>(), B, false, st);
+  const dim3 grid((unsigned)ceil_div((int64_t)p.L * g.ncols, 256), (unsigned)p.nslots);
+  hipLaunchKernelGGL(iadj_gather_kernel, grid, dim3(256), 0, st, g, p.d_slots.as<Slot>(), 0, p.w_H.as<double>(),
+                     p.w_X.as<double>());
+  OSHT_HIP(hipGetLastError());
+  gemm_slots(p, kIadj, 0, p.nslots, st);
+  const int64_t tot = (int64_t)p.L * p.L * B;
+  hipLaunchKernelGGL(fwd_scatter_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, st, g, p.d_slots.as<Slot>(),
+                     p.w_Y.as<double>(), flmbar, -1.0);
+  OSHT_HIP(hipGetLastError());
+}
+
+void run_forward_adjoint(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st) {
+  ensure_workspace(p, B);
+  const Geo g = geo(p, B);
+  const dim3 blk(256);
+  for (int am = 0; am < p.L; ++am) {
+    int s0, s1;
+    level_slots(p, am, s0, s1);
+    const int rows = p.L;  // K + |m| <= L and R <= L
+    const unsigned gx = (unsigned)ceil_div((int64_t)rows * g.ncols, 256);
+    std::vector<int> list;
+    if (p.spin == 0 || am == 0) list = {s0}; else list = {s0, s1 - 1};
+    for (int sl : list) {
+      hipLaunchKernelGGL(fadj_gather_kernel, dim3(gx, 1), blk, 0, st, g, p.d_slots.as<Slot>(), sl, flmbar,
+                         p.w_H.as<double>(), p.w_X.as<double>());
+      OSHT_HIP(hipGetLastError());
+      gemm_slots(p, kFadj, sl, sl + 1, st);
+      hipLaunchKernelGGL(fadj_scatter_kernel, dim3(gx, 1), blk, 0, st, g, p.d_slots.as<Slot>(), sl,
+                         p.w_Y.as<double>(), p.w_H.as<double>());
+      OSHT_HIP(hipGetLastError());
+    }
+  }
+  launch_ring_synthesis(p, p.w_H.as<double>(), 1, nullptr, fbar, B, st);
+}
+
+}  // namespace osht

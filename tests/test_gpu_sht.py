@@ -1,0 +1,162 @@
+"""GPU parity: every transform of the HIP library against the FP64 oracle,
+element by element, through the C ABI (via the thin Python binding)."""
+
+import numpy as np
+import pytest
+
+from tests import inputs
+from tests.gpu_util import golden_theta, oracle_plan, relmax, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+_plans = {}
+
+
+def gpu_plan(L, s=0, placement="greedy"):
+    from paper_1403_4661_amd import Plan
+    key = (L, s, placement)
+    if key not in _plans:
+        _plans[key] = Plan(L, s, placement=placement)
+    return _plans[key]
+
+
+_oplans = {}
+
+
+def oplan(L, s=0, placement="greedy"):
+    key = (L, s, placement)
+    if key not in _oplans:
+        _oplans[key] = oracle_plan(L, s, placement)
+    return _oplans[key]
+
+
+def test_plan_basics_L32():
+    p = gpu_plan(32)
+    info = p.info()
+    assert info["L"] == 32 and info["nsamples"] == 32 * 32 and info["ncoeffs"] == 32 * 32
+    assert info["max_inv_residual"] < 1e-12
+    assert p.theta_numerators() == golden_theta(32).tolist()
+
+
+# (L, B, spin, weighted, seed): config 1 first, then ragged tiles and edges
+CASES = [
+    (32, 1, 0, False, 0),
+    (1, 1, 0, False, 1),
+    (2, 2, 0, False, 2),
+    (33, 3, 0, False, 3),
+    (65, 2, 0, False, 4),
+    (100, 17, 0, True, 5),
+    (16, 2, 2, False, 6),
+    (16, 2, -2, False, 7),
+    (21, 1, 1, False, 8),
+]
+
+
+@pytest.mark.parametrize("L,B,s,weighted,seed", CASES)
+def test_inverse_matches_oracle(L, B, s, weighted, seed):
+    flm = inputs.coeffs(L, B, seed=seed, weighted=weighted, spin=s)
+    ref = __import__("oracle").sht.inverse(oplan(L, s), flm)
+    got = to_host(gpu_plan(L, s).inverse(to_dev(flm)))
+    assert relmax(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("L,B,s,weighted,seed", [c for c in CASES if c[2] == 0])
+def test_forward_matches_oracle(L, B, s, weighted, seed):
+    from oracle import sht
+    op = oplan(L, s)
+    f = sht.inverse(op, inputs.coeffs(L, B, seed=seed, weighted=weighted))
+    ref = sht.forward(op, f)
+    got = to_host(gpu_plan(L, s).forward(to_dev(f)))
+    assert relmax(got, ref) < 1e-11
+
+
+@pytest.mark.parametrize("L", [16, 33])
+def test_forward_random_samples_matches_oracle(L):
+    """Experiment 2 input: random samples are band-limited on this scheme."""
+    from oracle import sht
+    f = inputs.samples_uniform(L, 2, seed=L)
+    ref = sht.forward(oplan(L), f)
+    got = to_host(gpu_plan(L).forward(to_dev(f)))
+    assert relmax(got, ref) < 1e-11
+
+
+@pytest.mark.parametrize("s", [2, -2, 1])
+def test_spin_forward_small_L(s):
+    """Spin forward (Sec. III-G) at L = 6, where the order-wise elimination is
+    still accurate; larger L is unstable on this scheme in FP64 for both the
+    oracle and the GPU."""
+    from oracle import sht
+    L = 6
+    flm = inputs.coeffs(L, 2, seed=11, spin=s)
+    f = sht.inverse(oplan(L, s), flm)
+    ref = sht.forward(oplan(L, s), f)
+    got = to_host(gpu_plan(L, s).forward(to_dev(f)))
+    assert relmax(got, ref) < 1e-10
+    assert relmax(got, flm) < 1e-9
+
+
+@pytest.mark.parametrize("L,B,s", [(32, 2, 0), (33, 3, 0), (17, 2, 2), (12, 1, -1)])
+def test_adjoints_match_oracle(L, B, s):
+    from oracle import sht
+    rng = np.random.default_rng(L + 100 * abs(s) + (s < 0))
+    x = rng.standard_normal((B, L * L)) + 1j * rng.standard_normal((B, L * L))
+    y = inputs.coeffs(L, B, seed=L, spin=s)
+    p = gpu_plan(L, s)
+    ia = to_host(p.inverse_adjoint(to_dev(x)))
+    assert relmax(ia, sht.inverse_adjoint(oplan(L, s), x)) < 1e-12
+    if s == 0 or L <= 12:
+        fa = to_host(p.forward_adjoint(to_dev(y)))
+        assert relmax(fa, sht.forward_adjoint(oplan(L, s), y)) < 1e-10
+    # dot-product identities on the GPU results themselves
+    inv_y = to_host(p.inverse(to_dev(y)))
+    assert abs(np.vdot(inv_y, x) - np.vdot(y, ia)) <= 1e-12 * abs(np.vdot(inv_y, x))
+
+
+def test_config2_L512_forward_inverse():
+    """L = 512, batch 1, flm ~ N(0,1)(1+l)^-1 (seed 1): both directions."""
+    from oracle import sht
+    L = 512
+    flm = inputs.coeffs(L, 1, seed=1, weighted=True)
+    op = oplan(L)
+    f_ref = sht.inverse(op, flm)
+    p = gpu_plan(L)
+    f = to_host(p.inverse(to_dev(flm)))
+    assert relmax(f, f_ref) < 1e-12
+    flm_gpu = to_host(p.forward(to_dev(f_ref)))
+    assert relmax(flm_gpu, sht.forward(op, f_ref)) < 1e-11
+    assert relmax(flm_gpu, flm) < 1e-11
+
+
+def test_deterministic_bitwise():
+    L, B = 40, 3
+    p = gpu_plan(L)
+    x = to_dev(inputs.coeffs(L, B, seed=9))
+    a, b = to_host(p.inverse(x)), to_host(p.inverse(x))
+    assert np.array_equal(a, b)
+    fa, fb = to_host(p.forward(to_dev(a))), to_host(p.forward(to_dev(a)))
+    assert np.array_equal(fa, fb)
+
+
+def test_bad_arguments_rejected():
+    import torch
+    from paper_1403_4661_amd import OshtError
+    p = gpu_plan(8)
+    x = torch.zeros((2, 64), dtype=torch.complex128, device="cuda")
+    with pytest.raises(OshtError):
+        p.inverse(x, out=x)  # aliasing
+    with pytest.raises(TypeError):
+        p.inverse(x.to(torch.complex64))
+    with pytest.raises(ValueError):
+        p.inverse(torch.zeros((2, 63), dtype=torch.complex128, device="cuda"))
+
+
+def test_alternating_placement_L20():
+    from oracle import sht
+    L = 20
+    flm = inputs.coeffs(L, 1, seed=12)
+    op = oplan(L, 0, "alternating")
+    p = gpu_plan(L, 0, "alternating")
+    assert p.theta_numerators() == op.num.tolist()
+    f = sht.inverse(op, flm)
+    assert relmax(to_host(p.inverse(to_dev(flm))), f) < 1e-12
+    assert relmax(to_host(p.forward(to_dev(f))), sht.forward(op, f)) < 1e-10
