@@ -135,6 +135,21 @@ int osht_inverse_adjoint(const osht_plan_t* plan, const void* f_bar, void* flm_b
 int osht_forward_adjoint(const osht_plan_t* plan, const void* flm_bar, void* f_bar,
                          int64_t batch, hipStream_t stream);
 
+/*
+ * Kernel timing.  With profiling enabled on a plan, each launch of the
+ * library's hot kernels made by that plan is bracketed by a pair of HIP
+ * events recorded on the launch stream; osht_plan_kernel_time waits for the
+ * pending events of one kernel name and returns the number of launches and
+ * their summed duration in milliseconds since profiling was (re)enabled.
+ * Names: "apply_inverse", "apply_forward", "apply_inverse_adjoint",
+ * "apply_forward_adjoint" (order-wise GEMMs), "ring_analysis",
+ * "ring_synthesis" (ring DFTs), "gather_forward", "gather_forward_adjoint".
+ * Unknown names return zero launches.  Enabling resets all counters.
+ */
+int osht_plan_set_profiling(osht_plan_t* plan, int enable);
+int osht_plan_kernel_time(osht_plan_t* plan, const char* name, int64_t* launches,
+                          double* total_ms);
+
 /* Human-readable message for a return code (static storage). */
 const char* osht_strerror(int code);
 /* Detail of the last error raised on the calling thread (thread-local

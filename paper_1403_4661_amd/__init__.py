@@ -71,6 +71,16 @@ class Plan:
         _lib.check(lib().osht_plan_theta(self._h, num))
         return [int(v) for v in num]
 
+    def set_profiling(self, enable=True):
+        """Event timing of the library's named kernel launches (resets counters)."""
+        _lib.check(lib().osht_plan_set_profiling(self._h, 1 if enable else 0))
+
+    def kernel_time(self, name):
+        """(launches, total milliseconds) of a named kernel since profiling was enabled."""
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        _lib.check(lib().osht_plan_kernel_time(self._h, name.encode(), ctypes.byref(n), ctypes.byref(ms)))
+        return int(n.value), float(ms.value)
+
     # -- transforms ---------------------------------------------------------
     def _run(self, fn, x, out=None):
         import torch

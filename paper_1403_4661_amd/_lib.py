@@ -36,6 +36,8 @@ EXPORTED = (
     "osht_forward_adjoint",
     "osht_strerror",
     "osht_last_error_message",
+    "osht_plan_set_profiling",
+    "osht_plan_kernel_time",
 )
 
 
@@ -89,6 +91,9 @@ def lib():
         fn = getattr(L, name)
         fn.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
         fn.restype = ctypes.c_int
+    L.osht_plan_set_profiling.argtypes = [vp, ctypes.c_int]
+    L.osht_plan_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_double)]
     L.osht_strerror.argtypes = [ctypes.c_int]
     L.osht_strerror.restype = ctypes.c_char_p
     L.osht_last_error_message.argtypes = []

@@ -245,4 +245,39 @@ int osht_forward_adjoint(const osht_plan_t* plan, const void* flm_bar, void* f_b
                        [&](Plan& p, const double* a, double* b) { osht::run_forward_adjoint(p, a, b, batch, stream); });
 }
 
+int osht_plan_set_profiling(osht_plan_t* plan, int enable) {
+  if (!plan) return fail(OSHT_EINVAL, "plan is NULL");
+  Plan& p = plan->p;
+  try {
+    std::lock_guard<std::mutex> lk(p.mu);
+    DeviceGuard g(p.device);
+    p.prof.reset();
+    p.prof.enabled = enable != 0;
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  }
+  return OSHT_OK;
+}
+
+int osht_plan_kernel_time(osht_plan_t* plan, const char* name, int64_t* launches, double* total_ms) {
+  if (!plan || !name || !launches || !total_ms) return fail(OSHT_EINVAL, "NULL argument");
+  Plan& p = plan->p;
+  try {
+    std::lock_guard<std::mutex> lk(p.mu);
+    DeviceGuard g(p.device);
+    *launches = 0;
+    *total_ms = 0.0;
+    for (auto& kv : p.prof.stats) {
+      if (kv.first == name) {
+        p.prof.flush(kv.second);
+        *launches = kv.second.count;
+        *total_ms = kv.second.ms;
+      }
+    }
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  }
+  return OSHT_OK;
+}
+
 }  // extern "C"

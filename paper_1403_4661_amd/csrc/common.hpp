@@ -103,6 +103,51 @@ struct RingDesc {
   int64_t off;    // offset of the chirp spectrum (M complex) in chirp table
 };
 
+// Event-pair timing of named kernel launches (see osht_plan_set_profiling).
+struct Profiler {
+  struct Stat {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    int64_t count = 0;
+    double ms = 0.0;
+  };
+  bool enabled = false;
+  std::vector<std::pair<std::string, Stat>> stats;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get();
+  Stat& stat(const char* name);
+  void reset();
+  void flush(Stat& s);
+  ~Profiler();
+};
+
+// Blocked forward sweep (built once per plan).  Levels |m| are processed in
+// blocks [q0, q1), highest first; the unknowns of block i are the alias rows
+// (m, k), q0 <= |m| <= k < q1, that receive aliases from other orders of the
+// same block (see sweep.hip).
+struct FwdBlocks {
+  int b = 1;                                   // levels per block
+  std::vector<int32_t> q0, q1;                 // per block
+  std::vector<int32_t> slot_ptr, slot_list;    // block -> slots
+  std::vector<int32_t> unk_ptr;                // block -> unknowns [u0, u1)
+  std::vector<int32_t> lev_blk_ptr, lev_ptr;   // block -> levels -> unknown offsets
+  std::vector<int32_t> unk_slot, unk_r, unk_m; // per unknown
+  std::vector<int32_t> src_ptr, src_slot, src_row, src_m;
+  std::vector<int64_t> w_ptr;                  // per unknown -> W entries
+  std::vector<int32_t> w_col;                  // block-local unknown index
+  std::vector<int64_t> w_idx;                  // element of d_Q holding the value
+  int max_unk = 0;
+  void clear_host() {
+    for (auto* v : {&q0, &q1, &slot_ptr, &slot_list, &unk_ptr, &lev_blk_ptr, &lev_ptr, &unk_slot, &unk_r, &unk_m,
+                    &src_ptr, &src_slot, &src_row, &src_m, &w_col})
+      v->clear();
+    w_ptr.clear();
+    w_idx.clear();
+    max_unk = 0;
+  }
+  DevBuf d_slot_list, d_lev_ptr, d_unk_slot, d_unk_r, d_unk_m, d_src_ptr, d_src_slot, d_src_row, d_src_m,
+      d_w_ptr, d_w_col, d_w_val;
+};
+
 struct Plan {
   int L = 0, spin = 0;
   uint32_t flags = 0;
@@ -119,13 +164,37 @@ struct Plan {
   DevBuf d_rings, d_chirp, d_twiddle;
   int max_logM = 0;
   // per-call workspace (grown on demand)
-  DevBuf w_X, w_Y, w_H, w_T;
+  DevBuf w_X, w_Y, w_H, w_T, w_D;
+  FwdBlocks fb;
+  std::vector<int32_t> h_btask_ptr;   // per block: [fwd begin, corr begin, end) into d_btask
+  DevBuf d_btask;
   DevBuf d_gdesc, d_gtask;    // GEMM descriptors for the transforms
   int64_t ws_batch = 0;
   std::vector<GemmDesc> h_gdesc;
   std::vector<GemmTask> h_gtask;
   std::mutex mu;
+  Profiler prof;
   int64_t device_bytes() const;
+};
+
+// RAII bracket: events around the launches made in its scope.
+struct ProfScope {
+  Profiler& P;
+  const char* name;
+  hipStream_t st;
+  hipEvent_t e0 = nullptr;
+  ProfScope(Profiler& p, const char* n, hipStream_t s) : P(p), name(n), st(s) {
+    if (P.enabled) {
+      e0 = P.get();
+      OSHT_HIP(hipEventRecord(e0, st));
+    }
+  }
+  ~ProfScope() {
+    if (e0) {
+      hipEvent_t e1 = P.get();
+      if (hipEventRecord(e1, st) == hipSuccess) P.stat(name).pending.emplace_back(e0, e1);
+    }
+  }
 };
 
 // ---------------------------------------------------------------- launchers
@@ -148,6 +217,10 @@ void build_chirps(Plan& p);
 // unnormalised (scale 1)
 void launch_ring_analysis(const Plan& p, const double* f, double* H, int64_t B, bool normalise,
                           hipStream_t st);
+
+// blocked forward sweep (sweep.hip)
+void build_fwd_blocks(Plan& p, int b);
+void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st);
 
 // placement (theta.cpp)
 int theta_greedy(int L, int32_t* num_out, double* kappa_out);

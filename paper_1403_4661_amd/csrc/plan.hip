@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <string>
 
 #include "common.hpp"
@@ -421,6 +422,9 @@ void build_plan(Plan& p) {
     OSHT_HIP(hipDeviceSynchronize());
   }
   build_chirps(p);
+  int b = 64;
+  if (const char* env = std::getenv("OSHT_FWD_BLOCK")) b = std::max(1, std::atoi(env));
+  build_fwd_blocks(p, b);
   OSHT_HIP(hipDeviceSynchronize());
 }
 

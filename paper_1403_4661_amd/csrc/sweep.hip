@@ -1,0 +1,256 @@
+// Blocked forward sweep (Procedure 1 with the order loop taken b levels at
+// a time).
+//
+// Procedure 1 removes, before order m is solved, the aliases of every order
+// |m'| > |m| from the rings k >= |m| (Eq. signal_update).  In the Fourier
+// domain ring k receives order m' in bin (m' mod n_k), n_k = 2k+1, and
+// g_m[k] = H_k[m mod n_k] - sum_{m' = m (mod n_k), |m'| > k} G'_{m'}(theta_k).
+// An alias m' = m + j n_k (j != 0) has |m'| >= 2k+1-|m|, so within a block of
+// levels [q0, q1) only the rows k < (q1+|m|-1)/2 of an order receive aliases
+// from other orders of the same block.  For block [q0, q1):
+//   1. gather   h_m[k] = H_k[m mod n_k] - sum over solved orders (|m'| >= q1)
+//   2. GEMM     Y_m = Q_m h_m     (Q_m = [P_m^{-1}; A_m^top P_m^{-1}])
+//   3. solve    for the unknown alias rows u = (m, k) of the block:
+//                 delta_u = beta_u - sum_{u'} W_{u,u'} delta_{u'},
+//               beta_u = sum_{m'} (Y_{m'})[K(m') + k]   (= C_{m'} h_{m'} at ring k),
+//               W_{u,u'} = Q_{m'}[K(m') + k, k' - |m'|] for u' = (m', k');
+//               a triangular system solved level by level (descending |m|),
+//   4. correct  Y_m -= Q_m[:, 0:q1-|m|] delta_m   (so Y_m = Q_m (h_m - delta_m)).
+// Afterwards Y_m holds f_m and the exact aliases G'_m on the rings k < |m|,
+// which later blocks read in step 1.  All sums run in a fixed order.
+
+#include <algorithm>
+#include <cstdlib>
+
+#include "xform.hpp"
+
+namespace osht {
+
+namespace {
+
+__global__ __launch_bounds__(256) void block_gather_kernel(Geo g, const Slot* __restrict__ slots,
+                                                           const int32_t* __restrict__ slot_list, int q1,
+                                                           const double* __restrict__ H, const double* __restrict__ Y,
+                                                           double* __restrict__ X) {
+  const int slot = slot_list[blockIdx.y];
+  const Slot sl = slots[slot];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = e / g.ncols, col = e % g.ncols;
+  if (r >= sl.R) return;
+  int sgn, b, part, m;
+  decode_col(g, sl, col, sgn, b, part, m);
+  const int am = m < 0 ? -m : m;
+  const int k = am + r, n = 2 * k + 1;
+  const int bin = pmod(m, n);
+  double v = H[(((int64_t)k * k + bin) * g.B + b) * 2 + part];
+  const int start = bin - ((bin + g.L - 1) / n) * n;
+  for (int mp = start; mp <= g.L - 1; mp += n) {
+    const int amp = mp < 0 ? -mp : mp;
+    if (mp == m || amp < q1) continue;  // only orders solved in earlier blocks
+    v -= Y[alias_index(g, slots, mp, k, b, part)];
+  }
+  X[((int64_t)slot * g.L + r) * g.ncols + col] = v;
+}
+
+__device__ __forceinline__ int order_col(const Geo& g, int m, int j) {
+  return (g.s == 0 && m < 0) ? 2 * g.B + j : j;
+}
+
+// One workgroup per map-part column j (0 .. 2B-1): solves the block's alias
+// unknowns level by level, writes delta into D[slot][r][col].
+__global__ __launch_bounds__(256) void delta_solve_kernel(Geo g, int u0, int nlev, const int32_t* __restrict__ lev_ptr,
+                                                          const int32_t* __restrict__ unk_slot,
+                                                          const int32_t* __restrict__ unk_r,
+                                                          const int32_t* __restrict__ unk_m,
+                                                          const int32_t* __restrict__ src_ptr,
+                                                          const int32_t* __restrict__ src_slot,
+                                                          const int32_t* __restrict__ src_row,
+                                                          const int32_t* __restrict__ src_m,
+                                                          const int64_t* __restrict__ w_ptr,
+                                                          const int32_t* __restrict__ w_col,
+                                                          const double* __restrict__ w_val, const double* __restrict__ Y,
+                                                          double* __restrict__ D, int bD) {
+  extern __shared__ double dl[];
+  const int j = blockIdx.x;
+  for (int lv = 0; lv < nlev; ++lv) {
+    for (int u = lev_ptr[lv] + threadIdx.x; u < lev_ptr[lv + 1]; u += blockDim.x) {
+      double acc = 0.0;
+      for (int s = src_ptr[u]; s < src_ptr[u + 1]; ++s)
+        acc += Y[((int64_t)src_slot[s] * g.L + src_row[s]) * g.ncols + order_col(g, src_m[s], j)];
+      for (int64_t w = w_ptr[u]; w < w_ptr[u + 1]; ++w) acc -= w_val[w] * dl[w_col[w]];
+      dl[u - u0] = acc;
+      D[((int64_t)unk_slot[u] * bD + unk_r[u]) * g.ncols + order_col(g, unk_m[u], j)] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void fill_zero_kernel(double* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+__global__ void gather_values_kernel(const double* __restrict__ src, const int64_t* __restrict__ idx,
+                                     double* __restrict__ dst, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
+template <class T>
+void put_vec(DevBuf& d, const std::vector<T>& h) {
+  d.alloc(std::max<size_t>(h.size(), 1) * sizeof(T));
+  if (!h.empty()) OSHT_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+}  // namespace
+
+void build_fwd_blocks(Plan& p, int b) {
+  FwdBlocks& fb = p.fb;
+  fb.clear_host();
+  fb.b = std::max(1, std::min(b, p.L));
+  const int L = p.L, s = p.spin;
+  auto slot_of = [&](int m) { return s == 0 ? std::abs(m) : m + L - 1; };
+  auto Kof = [&](int m) { return L - std::max(std::abs(m), std::abs(s)); };
+  fb.slot_ptr.push_back(0);
+  fb.unk_ptr.push_back(0);
+  fb.lev_blk_ptr.push_back(0);
+  fb.src_ptr.push_back(0);
+  fb.w_ptr.push_back(0);
+  for (int q1 = L; q1 > 0; q1 -= fb.b) {
+    const int q0 = std::max(0, q1 - fb.b);
+    fb.q0.push_back(q0);
+    fb.q1.push_back(q1);
+    // slots of the block (descending level)
+    for (int am = q1 - 1; am >= q0; --am) {
+      fb.slot_list.push_back(slot_of(am));
+      if (s != 0 && am > 0) fb.slot_list.push_back(slot_of(-am));
+    }
+    fb.slot_ptr.push_back((int32_t)fb.slot_list.size());
+    // unknowns, level by level; map (m, k) -> block-local index
+    const int u0 = (int)fb.unk_m.size();
+    std::vector<std::vector<int>> local_of(2 * L);  // index by m + L - 1, vector over k - |m|
+    struct Unk { int m, k; std::vector<int> src; };
+    std::vector<Unk> unks;
+    for (int am = q1 - 1; am >= q0; --am) {
+      fb.lev_ptr.push_back(u0 + (int)unks.size());
+      for (int m : {am, -am}) {
+        if (am == 0 && m != 0) continue;
+        for (int k = am; k < q1; ++k) {
+          const int n = 2 * k + 1;
+          std::vector<int> src;
+          const int bin = ((m % n) + n) % n;
+          const int start = bin - ((bin + L - 1) / n) * n;
+          for (int mp = start; mp <= L - 1; mp += n) {
+            const int amp = std::abs(mp);
+            if (mp == m || amp >= q1 || amp < q0 || amp <= k) continue;
+            src.push_back(mp);
+          }
+          if (src.empty()) continue;
+          std::vector<int>& lo = local_of[m + L - 1];
+          if (lo.empty()) lo.assign(q1 - am, -1);
+          lo[k - am] = (int)unks.size();
+          unks.push_back(Unk{m, k, src});
+        }
+        if (am == 0) break;
+      }
+    }
+    fb.lev_ptr.push_back(u0 + (int)unks.size());
+    fb.lev_blk_ptr.push_back((int32_t)fb.lev_ptr.size());
+    for (const Unk& u : unks) {
+      fb.unk_m.push_back(u.m);
+      fb.unk_slot.push_back(slot_of(u.m));
+      fb.unk_r.push_back(u.k - std::abs(u.m));
+      for (int mp : u.src) {
+        const int sp = slot_of(mp);
+        fb.src_slot.push_back(sp);
+        fb.src_row.push_back(Kof(mp) + u.k);
+        fb.src_m.push_back(mp);
+        // W row: alias row (K(m') + k) of Q_{m'} at the columns of m''s own unknowns
+        const std::vector<int>& lo = local_of[mp + L - 1];
+        const Slot& sl = p.slots[sp];
+        for (size_t c = 0; c < lo.size(); ++c) {
+          if (lo[c] < 0) continue;
+          fb.w_col.push_back(lo[c]);
+          fb.w_idx.push_back(sl.offQ + (int64_t)c * sl.ldQ + (Kof(mp) + u.k));
+        }
+      }
+      fb.src_ptr.push_back((int32_t)fb.src_slot.size());
+      fb.w_ptr.push_back((int64_t)fb.w_col.size());
+    }
+    fb.unk_ptr.push_back((int32_t)fb.unk_m.size());
+    fb.max_unk = std::max(fb.max_unk, (int)unks.size());
+  }
+  put_vec(fb.d_slot_list, fb.slot_list);
+  put_vec(fb.d_lev_ptr, fb.lev_ptr);
+  put_vec(fb.d_unk_slot, fb.unk_slot);
+  put_vec(fb.d_unk_r, fb.unk_r);
+  put_vec(fb.d_unk_m, fb.unk_m);
+  put_vec(fb.d_src_ptr, fb.src_ptr);
+  put_vec(fb.d_src_slot, fb.src_slot);
+  put_vec(fb.d_src_row, fb.src_row);
+  put_vec(fb.d_src_m, fb.src_m);
+  put_vec(fb.d_w_ptr, fb.w_ptr);
+  put_vec(fb.d_w_col, fb.w_col);
+  const int64_t nw = (int64_t)fb.w_idx.size();
+  fb.d_w_val.alloc(std::max<int64_t>(nw, 1) * sizeof(double));
+  if (nw > 0) {
+    DevBuf d_idx;
+    put_vec(d_idx, fb.w_idx);
+    hipLaunchKernelGGL(gather_values_kernel, dim3((unsigned)ceil_div(nw, 256)), dim3(256), 0, 0,
+                       p.d_Q.as<double>(), d_idx.as<int64_t>(), fb.d_w_val.as<double>(), nw);
+    OSHT_HIP(hipGetLastError());
+    OSHT_HIP(hipDeviceSynchronize());
+  }
+  fb.w_idx.clear();
+  fb.w_idx.shrink_to_fit();
+}
+
+void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {
+  ensure_workspace(p, B);
+  const Geo g = geo(p, B);
+  const FwdBlocks& fb = p.fb;
+  {
+    ProfScope ps(p.prof, "ring_analysis", st);
+    launch_ring_analysis(p, f, p.w_H.as<double>(), B, true, st);
+  }
+  const int bD = std::max(fb.b, 1);
+  const int64_t nD = (int64_t)p.nslots * bD * g.ncols;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nD, 256), 4096)), dim3(256), 0, st,
+                     p.w_D.as<double>(), nD);
+  OSHT_HIP(hipGetLastError());
+  const size_t lds = sizeof(double) * (size_t)std::max(fb.max_unk, 1);
+  if (lds > 65536)
+    OSHT_HIP(hipFuncSetAttribute((const void*)delta_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const int nblk = (int)fb.q0.size();
+  const GemmTask* bt = p.d_btask.as<GemmTask>();
+  for (int blk = 0; blk < nblk; ++blk) {
+    const int ns = fb.slot_ptr[blk + 1] - fb.slot_ptr[blk];
+    {
+      ProfScope ps(p.prof, "gather_forward", st);
+      hipLaunchKernelGGL(block_gather_kernel, dim3((unsigned)ceil_div((int64_t)p.L * g.ncols, 256), ns), dim3(256), 0,
+                         st, g, p.d_slots.as<Slot>(), fb.d_slot_list.as<int32_t>() + fb.slot_ptr[blk], fb.q1[blk],
+                         p.w_H.as<double>(), p.w_Y.as<double>(), p.w_X.as<double>());
+      OSHT_HIP(hipGetLastError());
+    }
+    const int t0 = p.h_btask_ptr[2 * blk], t1 = p.h_btask_ptr[2 * blk + 1], t2 = p.h_btask_ptr[2 * blk + 2];
+    gemm_tasks_launch(p, bt + t0, t1 - t0, "apply_forward", st);
+    const int u0 = fb.unk_ptr[blk], u1 = fb.unk_ptr[blk + 1];
+    if (u1 > u0) {
+      const int lv0 = fb.lev_blk_ptr[blk], lv1 = fb.lev_blk_ptr[blk + 1];
+      {
+        ProfScope ps(p.prof, "delta_solve", st);
+        hipLaunchKernelGGL(delta_solve_kernel, dim3((unsigned)(2 * B)), dim3(256), lds, st, g, u0, lv1 - lv0 - 1,
+                           fb.d_lev_ptr.as<int32_t>() + lv0, fb.d_unk_slot.as<int32_t>(), fb.d_unk_r.as<int32_t>(),
+                           fb.d_unk_m.as<int32_t>(), fb.d_src_ptr.as<int32_t>(), fb.d_src_slot.as<int32_t>(),
+                           fb.d_src_row.as<int32_t>(), fb.d_src_m.as<int32_t>(), fb.d_w_ptr.as<int64_t>(),
+                           fb.d_w_col.as<int32_t>(), fb.d_w_val.as<double>(), p.w_Y.as<double>(), p.w_D.as<double>(),
+                           bD);
+        OSHT_HIP(hipGetLastError());
+      }
+      gemm_tasks_launch(p, bt + t1, t2 - t1, "apply_forward_correction", st);
+    }
+  }
+  launch_fwd_scatter(p, p.w_Y.as<double>(), flm, B, st);
+}
+
+}  // namespace osht

@@ -23,7 +23,7 @@
 // and A_{-m} = (-1)^m A_m; the sign is applied where coefficients enter or
 // leave the slot buffers.
 
-#include "common.hpp"
+#include "xform.hpp"
 
 namespace osht {
 
@@ -31,46 +31,6 @@ void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, cons
                            hipStream_t st);
 
 namespace {
-
-struct Geo {
-  int L, s, B, ncols;
-};
-
-__device__ __forceinline__ int pmod(int a, int n) {
-  const int r = a % n;
-  return r < 0 ? r + n : r;
-}
-
-// decode a slot column into (sgn, map, part) and the signed order
-__device__ __forceinline__ void decode_col(const Geo& g, const Slot& sl, int col, int& sgn, int& b, int& part, int& m) {
-  if (g.s == 0) {
-    sgn = col / (2 * g.B);
-    const int r = col - sgn * 2 * g.B;
-    b = r >> 1;
-    part = r & 1;
-    m = sgn ? -sl.m : sl.m;
-  } else {
-    sgn = 0;
-    b = col >> 1;
-    part = col & 1;
-    m = sl.m;
-  }
-}
-
-// Y-buffer location of G'_{m'}(theta_k) for the forward pass (the bottom
-// rows of the slot of order m'), for map b / part.
-__device__ __forceinline__ int64_t alias_index(const Geo& g, const Slot* __restrict__ slots, int mp, int k, int b, int part) {
-  int slot, col;
-  if (g.s == 0) {
-    slot = mp < 0 ? -mp : mp;
-    col = (mp < 0 ? 2 * g.B : 0) + 2 * b + part;
-  } else {
-    slot = mp + g.L - 1;
-    col = 2 * b + part;
-  }
-  const int K = slots[slot].K;
-  return ((int64_t)slot * g.L + K + k) * g.ncols + col;
-}
 
 // Inverse: X[slot][i][col] = coefficient (l0+i, m) of map b (sign-adjusted).
 __global__ __launch_bounds__(256) void inv_gather_kernel(Geo g, const Slot* __restrict__ slots, int slot0,
@@ -206,26 +166,38 @@ __global__ __launch_bounds__(256) void fadj_scatter_kernel(Geo g, const Slot* __
 }  // namespace
 
 // ---------------------------------------------------------------- host side
-namespace {
+const char* const kApplyName[kNumDir] = {"apply_inverse", "apply_forward", "apply_inverse_adjoint",
+                                         "apply_forward_adjoint", "apply_forward_correction"};
 
-enum { kInv = 0, kFwd = 1, kIadj = 2, kFadj = 3 };
-
+// Workspace and GEMM descriptors for batch B (rebuilt when B or the buffers
+// change).  Descriptor d = dir * nslots + slot; tasks of all directions are
+// kept in descriptor order (d_gtask), and the blocked forward has its own
+// per-block task lists (d_btask) for its two GEMMs.
 void ensure_workspace(Plan& p, int64_t B) {
   const int64_t ncols = p.ncols_per_map * B;
   const size_t xy = sizeof(double) * (size_t)p.nslots * p.L * ncols;
   const size_t hb = sizeof(double) * 2 * (size_t)p.L * p.L * B;
-  const bool grow = (xy > p.w_X.bytes) || (hb > p.w_H.bytes);
+  const size_t db = sizeof(double) * (size_t)p.nslots * std::max(p.fb.b, 1) * ncols;
+  const bool grow = (xy > p.w_X.bytes) || (hb > p.w_H.bytes) || (db > p.w_D.bytes);
   p.w_X.reserve(xy);
   p.w_Y.reserve(xy);
   p.w_H.reserve(hb);
+  p.w_D.reserve(db);
   if (!grow && p.ws_batch == B && !p.h_gdesc.empty()) return;
-  // GEMM descriptors for the four directions, one per slot each
   p.h_gdesc.clear();
   double* X = p.w_X.as<double>();
   double* Y = p.w_Y.as<double>();
+  double* D = p.w_D.as<double>();
   const double* A = p.d_A.as<double>();
   const double* Q = p.d_Q.as<double>();
-  for (int dir = 0; dir < 4; ++dir) {
+  const int bD = std::max(p.fb.b, 1);
+  std::vector<int32_t> wcorr(p.nslots, 0);  // correction width per slot
+  for (size_t blk = 0; blk + 1 < p.fb.slot_ptr.size(); ++blk)
+    for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) {
+      const int slot = p.fb.slot_list[i];
+      wcorr[slot] = p.fb.q1[blk] - std::abs(p.slots[slot].m);
+    }
+  for (int dir = 0; dir < kNumDir; ++dir) {
     for (int i = 0; i < p.nslots; ++i) {
       const Slot& sl = p.slots[i];
       const int am = std::abs(sl.m);
@@ -239,19 +211,60 @@ void ensure_workspace(Plan& p, int64_t B) {
       if (dir == kFwd) { d.A = Q + sl.offQ; d.sAr = 1; d.sAc = sl.ldQ; d.M = sl.K + am; d.K = sl.R; }
       if (dir == kIadj) { d.A = A + sl.offA; d.sAr = sl.ldA; d.sAc = 1; d.M = sl.K; d.K = p.L; }
       if (dir == kFadj) { d.A = Q + sl.offQ; d.sAr = sl.ldQ; d.sAc = 1; d.M = sl.R; d.K = sl.K + am; }
+      if (dir == kCorr) {  // Y -= Q[:, 0:w] D
+        d.A = Q + sl.offQ; d.sAr = 1; d.sAc = sl.ldQ; d.M = sl.K + am; d.K = std::min(wcorr[i], sl.R);
+        d.B = D + (int64_t)i * bD * ncols;
+        d.alpha = -1.0; d.beta = 1.0;
+      }
       p.h_gdesc.push_back(d);
     }
   }
   gemm_tasks(p.h_gdesc, p.h_gtask);
   upload(p.d_gdesc, p.h_gdesc);
   upload(p.d_gtask, p.h_gtask);
+  // per-block task lists of the blocked forward
+  std::vector<GemmTask> bt;
+  p.h_btask_ptr.clear();
+  const int nblk = (int)p.fb.q0.size();
+  for (int blk = 0; blk < nblk; ++blk) {
+    for (int pass = 0; pass < 2; ++pass) {
+      p.h_btask_ptr.push_back((int32_t)bt.size());
+      const int dir = pass == 0 ? kFwd : kCorr;
+      const bool has_unk = p.fb.unk_ptr[blk + 1] > p.fb.unk_ptr[blk];
+      if (pass == 1 && !has_unk) continue;
+      for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) {
+        const int d = dir * p.nslots + p.fb.slot_list[i];
+        const GemmDesc& g = p.h_gdesc[d];
+        if (g.K <= 0) continue;
+        for (int a = 0; a < (int)ceil_div(g.M, 64); ++a)
+          for (int c = 0; c < (int)ceil_div(g.N, 64); ++c) bt.push_back(GemmTask{d, a, c, 0});
+      }
+    }
+  }
+  p.h_btask_ptr.push_back((int32_t)bt.size());
+  upload(p.d_btask, bt);
   p.ws_batch = B;
 }
+
+void launch_fwd_scatter(const Plan& p, const double* Y, double* flm, int64_t B, hipStream_t st) {
+  const Geo g = geo(p, B);
+  const int64_t tot = (int64_t)p.L * p.L * B;
+  hipLaunchKernelGGL(fwd_scatter_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, st, g, p.d_slots.as<Slot>(), Y,
+                     flm, -1.0);
+  OSHT_HIP(hipGetLastError());
+}
+
+void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, const char* prof_name, hipStream_t st) {
+  if (count <= 0) return;
+  ProfScope ps(p.prof, prof_name, st);
+  launch_gemm_f64(p.d_gdesc.as<GemmDesc>(), d_tasks, count, st);
+}
+
+namespace {
 
 // task range [first, count) of the GEMMs for direction dir, slots [s0, s1)
 void task_range(const Plan& p, int dir, int s0, int s1, int& first, int& count) {
   const int d0 = dir * p.nslots + s0, d1 = dir * p.nslots + s1;
-  // tasks are emitted in descriptor order
   int lo = 0, hi = (int)p.h_gtask.size();
   {
     int a = 0, b = hi;
@@ -267,13 +280,11 @@ void task_range(const Plan& p, int dir, int s0, int s1, int& first, int& count) 
   count = hi - lo;
 }
 
-void gemm_slots(const Plan& p, int dir, int s0, int s1, hipStream_t st) {
+void gemm_slots(Plan& p, int dir, int s0, int s1, hipStream_t st) {
   int first, count;
   task_range(p, dir, s0, s1, first, count);
-  launch_gemm_f64(p.d_gdesc.as<GemmDesc>(), p.d_gtask.as<GemmTask>() + first, count, st);
+  gemm_tasks_launch(p, p.d_gtask.as<GemmTask>() + first, count, kApplyName[dir], st);
 }
-
-Geo geo(const Plan& p, int64_t B) { return Geo{p.L, p.spin, (int)B, (int)(p.ncols_per_map * B)}; }
 
 // slots of level am: spin 0 -> [am, am+1); spin s -> {-am, +am}
 void level_slots(const Plan& p, int am, int& s0, int& s1) {
@@ -292,13 +303,17 @@ void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t s
   hipLaunchKernelGGL(inv_gather_kernel, grid, dim3(256), 0, st, g, p.d_slots.as<Slot>(), 0, flm, p.w_X.as<double>());
   OSHT_HIP(hipGetLastError());
   gemm_slots(p, kInv, 0, p.nslots, st);
+  ProfScope ps(p.prof, "ring_synthesis", st);
   launch_ring_synthesis(p, nullptr, 0, p.w_Y.as<double>(), f, B, st);
 }
 
-void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {
+void run_forward_levels(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {
   ensure_workspace(p, B);
   const Geo g = geo(p, B);
-  launch_ring_analysis(p, f, p.w_H.as<double>(), B, true, st);
+  {
+    ProfScope ps(p.prof, "ring_analysis", st);
+    launch_ring_analysis(p, f, p.w_H.as<double>(), B, true, st);
+  }
   const dim3 blk(256);
   for (int am = p.L - 1; am >= 0; --am) {
     int s0, s1;
@@ -362,6 +377,11 @@ void run_forward_adjoint(Plan& p, const double* flmbar, double* fbar, int64_t B,
     }
   }
   launch_ring_synthesis(p, p.w_H.as<double>(), 1, nullptr, fbar, B, st);
+}
+
+void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {
+  if (p.fb.b > 1) run_forward_blocked(p, f, flm, B, st);
+  else run_forward_levels(p, f, flm, B, st);
 }
 
 }  // namespace osht
