@@ -136,6 +136,9 @@ struct FwdBlocks {
   std::vector<int32_t> w_col;                  // block-local unknown index
   std::vector<int64_t> w_idx;                  // element of d_Q holding the value
   int max_unk = 0;
+  int64_t max_w = 0;                           // max W entries in one block
+  int cpw = 8;                                 // delta-solve columns per workgroup
+  int lds_limit = 160 * 1024;
   void clear_host() {
     for (auto* v : {&q0, &q1, &slot_ptr, &slot_list, &unk_ptr, &lev_blk_ptr, &lev_ptr, &unk_slot, &unk_r, &unk_m,
                     &src_ptr, &src_slot, &src_row, &src_m, &w_col})
@@ -161,12 +164,13 @@ struct Plan {
   DevBuf d_cos, d_sin, d_cosh, d_sinh;
   DevBuf d_slots;
   DevBuf d_A, d_Q;            // FP64 blocks
-  DevBuf d_rings, d_chirp, d_twiddle;
+  DevBuf d_rings, d_chirp, d_twiddle, d_chirp_tab;
+  std::vector<int32_t> h_ring_logM;
   int max_logM = 0;
   // per-call workspace (grown on demand)
   DevBuf w_X, w_Y, w_H, w_T, w_D;
   FwdBlocks fb;
-  std::vector<int32_t> h_btask_ptr;   // per block: [fwd begin, corr begin, end) into d_btask
+  std::vector<int32_t> h_btask_ptr;   // per block: [fwd, corr, end) offsets into d_btask
   DevBuf d_btask;
   DevBuf d_gdesc, d_gtask;    // GEMM descriptors for the transforms
   int64_t ws_batch = 0;
@@ -206,8 +210,12 @@ void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t s
 void run_inverse_adjoint(Plan& p, const double* fbar, double* flmbar, int64_t B, hipStream_t st);
 void run_forward_adjoint(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st);
 
-// GEMM (gemm.hip): tasks and descriptors already on the device.
-void launch_gemm_f64(const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st);
+// GEMM (gemm.hip): tasks and descriptors already on the device.  All
+// descriptors of one launch share the operand layout: a_rowfast <=> sAr == 1
+// (A column-major), b_colfast <=> sBc == 1 (B row-major); other strides are
+// taken from each descriptor.
+void launch_gemm_f64(const GemmDesc* d_desc, const GemmTask* d_task, int ntask, bool a_rowfast, bool b_colfast,
+                     hipStream_t st);
 // Builds tasks for descriptors (64 x 64 tiles).
 void gemm_tasks(const std::vector<GemmDesc>& descs, std::vector<GemmTask>& tasks);
 

@@ -293,13 +293,13 @@ double newton_schulz(Plan& p, int s0, int s1, DevBuf& scratch, std::vector<doubl
   double best = INFINITY, last = INFINITY;
   int stall = 0;
   for (int it = 0; it < 120; ++it) {
-    launch_gemm_f64(gPX.as<GemmDesc>(), kPX.as<GemmTask>(), (int)tPX.size(), 0);
+    launch_gemm_f64(gPX.as<GemmDesc>(), kPX.as<GemmTask>(), (int)tPX.size(), true, false, 0);
     hipLaunchKernelGGL(ns_copy_kernel, dim3(64, ns), dim3(256), 0, 0, d_slots, s0, Q, scr, d_offXn.as<int64_t>(), 2.0, 0);
-    launch_gemm_f64(gXT.as<GemmDesc>(), kXT.as<GemmTask>(), (int)tXT.size(), 0);
+    launch_gemm_f64(gXT.as<GemmDesc>(), kXT.as<GemmTask>(), (int)tXT.size(), true, false, 0);
     hipLaunchKernelGGL(ns_copy_kernel, dim3(64, ns), dim3(256), 0, 0, d_slots, s0, Q, scr, d_offXn.as<int64_t>(), 1.0, 1);
     OSHT_HIP(hipGetLastError());
     if (it < 8) continue;
-    launch_gemm_f64(gXP.as<GemmDesc>(), kXP.as<GemmTask>(), (int)tXP.size(), 0);
+    launch_gemm_f64(gXP.as<GemmDesc>(), kXP.as<GemmTask>(), (int)tXP.size(), true, false, 0);
     hipLaunchKernelGGL(ns_resid_kernel, dim3(ns), dim3(256), 0, 0, d_slots, s0, scr, d_offE.as<int64_t>(), d_out.as<double>());
     OSHT_HIP(hipGetLastError());
     OSHT_HIP(hipMemcpy(res.data(), d_out.p, sizeof(double) * ns, hipMemcpyDeviceToHost));
@@ -324,7 +324,7 @@ double newton_schulz(Plan& p, int s0, int s1, DevBuf& scratch, std::vector<doubl
 
 int64_t Plan::device_bytes() const {
   return (int64_t)(d_cos.bytes + d_sin.bytes + d_cosh.bytes + d_sinh.bytes + d_slots.bytes + d_A.bytes + d_Q.bytes +
-                   d_rings.bytes + d_chirp.bytes + d_twiddle.bytes + w_X.bytes + w_Y.bytes + w_H.bytes + w_T.bytes +
+                   d_rings.bytes + d_chirp.bytes + d_twiddle.bytes + d_chirp_tab.bytes + w_X.bytes + w_Y.bytes + w_H.bytes + w_T.bytes +
                    d_gdesc.bytes + d_gtask.bytes);
 }
 
@@ -418,13 +418,20 @@ void build_plan(Plan& p) {
     DevBuf gd, gt;
     upload(gd, dC);
     upload(gt, tC);
-    launch_gemm_f64(gd.as<GemmDesc>(), gt.as<GemmTask>(), (int)tC.size(), 0);
+    launch_gemm_f64(gd.as<GemmDesc>(), gt.as<GemmTask>(), (int)tC.size(), true, false, 0);
     OSHT_HIP(hipDeviceSynchronize());
   }
   build_chirps(p);
-  int b = 64;
+  // Block size of the forward sweep: the largest b <= 32 (or OSHT_FWD_BLOCK)
+  // whose alias system fits the delta solve's LDS with 8 columns per group.
+  int b = 32;
   if (const char* env = std::getenv("OSHT_FWD_BLOCK")) b = std::max(1, std::atoi(env));
-  build_fwd_blocks(p, b);
+  for (;;) {
+    build_fwd_blocks(p, b);
+    const size_t need = sizeof(double) * ((size_t)p.fb.max_unk * p.fb.cpw + p.fb.max_w) + sizeof(int32_t) * p.fb.max_w;
+    if (need <= (size_t)p.fb.lds_limit || b == 1) break;
+    b = std::max(1, b * 3 / 4);
+  }
   OSHT_HIP(hipDeviceSynchronize());
 }
 

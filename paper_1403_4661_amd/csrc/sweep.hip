@@ -28,37 +28,48 @@ namespace osht {
 
 namespace {
 
+// One thread per (row r, complex column cc = sgn * B + b): both doubles of
+// the complex RHS entry, with the alias search shared by re and im.
 __global__ __launch_bounds__(256) void block_gather_kernel(Geo g, const Slot* __restrict__ slots,
                                                            const int32_t* __restrict__ slot_list, int q1,
-                                                           const double* __restrict__ H, const double* __restrict__ Y,
-                                                           double* __restrict__ X) {
+                                                           const double2* __restrict__ H, const double* __restrict__ Y,
+                                                           double2* __restrict__ X) {
   const int slot = slot_list[blockIdx.y];
   const Slot sl = slots[slot];
+  const int nc = g.ncols >> 1;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = e / g.ncols, col = e % g.ncols;
+  const int r = e / nc, cc = e - r * nc;
   if (r >= sl.R) return;
-  int sgn, b, part, m;
-  decode_col(g, sl, col, sgn, b, part, m);
+  const int sgn = (g.s == 0) ? cc / g.B : 0;
+  const int b = cc - sgn * g.B;
+  const int m = sgn ? -sl.m : sl.m;
   const int am = m < 0 ? -m : m;
   const int k = am + r, n = 2 * k + 1;
   const int bin = pmod(m, n);
-  double v = H[(((int64_t)k * k + bin) * g.B + b) * 2 + part];
+  double2 v = H[((int64_t)k * k + bin) * g.B + b];
   const int start = bin - ((bin + g.L - 1) / n) * n;
   for (int mp = start; mp <= g.L - 1; mp += n) {
     const int amp = mp < 0 ? -mp : mp;
     if (mp == m || amp < q1) continue;  // only orders solved in earlier blocks
-    v -= Y[alias_index(g, slots, mp, k, b, part)];
+    const double2 a = *reinterpret_cast<const double2*>(Y + alias_index(g, slots, mp, k, b, 0));
+    v.x -= a.x;
+    v.y -= a.y;
   }
-  X[((int64_t)slot * g.L + r) * g.ncols + col] = v;
+  X[((int64_t)slot * g.L + r) * nc + cc] = v;
 }
 
 __device__ __forceinline__ int order_col(const Geo& g, int m, int j) {
   return (g.s == 0 && m < 0) ? 2 * g.B + j : j;
 }
 
-// One workgroup per map-part column j (0 .. 2B-1): solves the block's alias
-// unknowns level by level, writes delta into D[slot][r][col].
-__global__ __launch_bounds__(256) void delta_solve_kernel(Geo g, int u0, int nlev, const int32_t* __restrict__ lev_ptr,
+// Alias unknowns of one block, solved level by level (descending |m|):
+//   delta_u = beta_u - sum_{u'} W_{u,u'} delta_{u'},
+//   beta_u  = sum over the alias sources m' of u = (m, k) of (Y_{m'})[K(m') + k].
+// The block's W (values and block-local columns) sits in LDS together with
+// delta for `cpw` columns; workgroup g handles columns [g*cpw, (g+1)*cpw) of
+// the 2B map-part columns.  Writes delta into D[slot][r][col].
+__global__ __launch_bounds__(512) void delta_solve_kernel(Geo g, int u0, int nu, int nlev, int cpw,
+                                                          const int32_t* __restrict__ lev_ptr,
                                                           const int32_t* __restrict__ unk_slot,
                                                           const int32_t* __restrict__ unk_r,
                                                           const int32_t* __restrict__ unk_m,
@@ -70,16 +81,40 @@ __global__ __launch_bounds__(256) void delta_solve_kernel(Geo g, int u0, int nle
                                                           const int32_t* __restrict__ w_col,
                                                           const double* __restrict__ w_val, const double* __restrict__ Y,
                                                           double* __restrict__ D, int bD) {
-  extern __shared__ double dl[];
-  const int j = blockIdx.x;
-  for (int lv = 0; lv < nlev; ++lv) {
-    for (int u = lev_ptr[lv] + threadIdx.x; u < lev_ptr[lv + 1]; u += blockDim.x) {
-      double acc = 0.0;
+  extern __shared__ double lds[];
+  const int64_t wbase = w_ptr[u0];
+  const int nw = (int)(w_ptr[u0 + nu] - wbase);
+  double* dl = lds;                                   // nu * cpw
+  double* wv = lds + (size_t)nu * cpw;                // nw
+  int32_t* wc = reinterpret_cast<int32_t*>(wv + nw);  // nw
+  const int j0 = blockIdx.x * cpw;
+  const int J = 2 * g.B;
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) {
+    wv[i] = w_val[wbase + i];
+    wc[i] = w_col[wbase + i];
+  }
+  // beta for every unknown and column of this group
+  for (int e = threadIdx.x; e < nu * cpw; e += blockDim.x) {
+    const int ul = e / cpw, jj = e - ul * cpw, j = j0 + jj;
+    double acc = 0.0;
+    if (j < J) {
+      const int u = u0 + ul;
       for (int s = src_ptr[u]; s < src_ptr[u + 1]; ++s)
         acc += Y[((int64_t)src_slot[s] * g.L + src_row[s]) * g.ncols + order_col(g, src_m[s], j)];
-      for (int64_t w = w_ptr[u]; w < w_ptr[u + 1]; ++w) acc -= w_val[w] * dl[w_col[w]];
-      dl[u - u0] = acc;
-      D[((int64_t)unk_slot[u] * bD + unk_r[u]) * g.ncols + order_col(g, unk_m[u], j)] = acc;
+    }
+    dl[e] = acc;
+  }
+  __syncthreads();
+  for (int lv = 0; lv < nlev; ++lv) {
+    const int a = lev_ptr[lv] - u0, b = lev_ptr[lv + 1] - u0;
+    for (int e = threadIdx.x; e < (b - a) * cpw; e += blockDim.x) {
+      const int ul = a + e / cpw, jj = e % cpw, j = j0 + jj;
+      const int u = u0 + ul;
+      double acc = dl[ul * cpw + jj];
+      const int w1 = (int)(w_ptr[u + 1] - wbase);
+      for (int w = (int)(w_ptr[u] - wbase); w < w1; ++w) acc -= wv[w] * dl[wc[w] * cpw + jj];
+      dl[ul * cpw + jj] = acc;
+      if (j < J) D[((int64_t)unk_slot[u] * bD + unk_r[u]) * g.ncols + order_col(g, unk_m[u], j)] = acc;
     }
     __syncthreads();
   }
@@ -203,6 +238,12 @@ void build_fwd_blocks(Plan& p, int b) {
   }
   fb.w_idx.clear();
   fb.w_idx.shrink_to_fit();
+  // LDS need of the delta solve per block: delta for cpw columns + W
+  fb.max_w = 0;
+  for (size_t blk = 0; blk + 1 < fb.unk_ptr.size(); ++blk) {
+    const int64_t nw = fb.w_ptr[fb.unk_ptr[blk + 1]] - fb.w_ptr[fb.unk_ptr[blk]];
+    fb.max_w = std::max<int64_t>(fb.max_w, nw);
+  }
 }
 
 void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {
@@ -218,36 +259,39 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
   hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nD, 256), 4096)), dim3(256), 0, st,
                      p.w_D.as<double>(), nD);
   OSHT_HIP(hipGetLastError());
-  const size_t lds = sizeof(double) * (size_t)std::max(fb.max_unk, 1);
-  if (lds > 65536)
-    OSHT_HIP(hipFuncSetAttribute((const void*)delta_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  OSHT_HIP(hipFuncSetAttribute((const void*)delta_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                fb.lds_limit));
   const int nblk = (int)fb.q0.size();
   const GemmTask* bt = p.d_btask.as<GemmTask>();
   for (int blk = 0; blk < nblk; ++blk) {
     const int ns = fb.slot_ptr[blk + 1] - fb.slot_ptr[blk];
     {
       ProfScope ps(p.prof, "gather_forward", st);
-      hipLaunchKernelGGL(block_gather_kernel, dim3((unsigned)ceil_div((int64_t)p.L * g.ncols, 256), ns), dim3(256), 0,
-                         st, g, p.d_slots.as<Slot>(), fb.d_slot_list.as<int32_t>() + fb.slot_ptr[blk], fb.q1[blk],
-                         p.w_H.as<double>(), p.w_Y.as<double>(), p.w_X.as<double>());
+      hipLaunchKernelGGL(block_gather_kernel, dim3((unsigned)ceil_div((int64_t)p.L * (g.ncols / 2), 256), ns), dim3(256),
+                         0, st, g, p.d_slots.as<Slot>(), fb.d_slot_list.as<int32_t>() + fb.slot_ptr[blk], fb.q1[blk],
+                         reinterpret_cast<const double2*>(p.w_H.as<double>()), p.w_Y.as<double>(),
+                         reinterpret_cast<double2*>(p.w_X.as<double>()));
       OSHT_HIP(hipGetLastError());
     }
-    const int t0 = p.h_btask_ptr[2 * blk], t1 = p.h_btask_ptr[2 * blk + 1], t2 = p.h_btask_ptr[2 * blk + 2];
-    gemm_tasks_launch(p, bt + t0, t1 - t0, "apply_forward", st);
-    const int u0 = fb.unk_ptr[blk], u1 = fb.unk_ptr[blk + 1];
-    if (u1 > u0) {
+    const int* tp = &p.h_btask_ptr[2 * blk];
+    gemm_tasks_launch(p, bt + tp[0], tp[1] - tp[0], true, "apply_forward", st);
+    const int u0 = fb.unk_ptr[blk], nu = fb.unk_ptr[blk + 1] - u0;
+    if (nu > 0) {
       const int lv0 = fb.lev_blk_ptr[blk], lv1 = fb.lev_blk_ptr[blk + 1];
+      const int64_t nw = fb.w_ptr[u0 + nu] - fb.w_ptr[u0];
+      const int cpw = fb.cpw;
+      const size_t lds = sizeof(double) * ((size_t)nu * cpw + nw) + sizeof(int32_t) * nw;
       {
         ProfScope ps(p.prof, "delta_solve", st);
-        hipLaunchKernelGGL(delta_solve_kernel, dim3((unsigned)(2 * B)), dim3(256), lds, st, g, u0, lv1 - lv0 - 1,
-                           fb.d_lev_ptr.as<int32_t>() + lv0, fb.d_unk_slot.as<int32_t>(), fb.d_unk_r.as<int32_t>(),
-                           fb.d_unk_m.as<int32_t>(), fb.d_src_ptr.as<int32_t>(), fb.d_src_slot.as<int32_t>(),
-                           fb.d_src_row.as<int32_t>(), fb.d_src_m.as<int32_t>(), fb.d_w_ptr.as<int64_t>(),
-                           fb.d_w_col.as<int32_t>(), fb.d_w_val.as<double>(), p.w_Y.as<double>(), p.w_D.as<double>(),
-                           bD);
+        hipLaunchKernelGGL(delta_solve_kernel, dim3((unsigned)ceil_div(2 * B, cpw)), dim3(512), lds, st, g, u0, nu,
+                           lv1 - lv0 - 1, cpw, fb.d_lev_ptr.as<int32_t>() + lv0, fb.d_unk_slot.as<int32_t>(),
+                           fb.d_unk_r.as<int32_t>(), fb.d_unk_m.as<int32_t>(), fb.d_src_ptr.as<int32_t>(),
+                           fb.d_src_slot.as<int32_t>(), fb.d_src_row.as<int32_t>(), fb.d_src_m.as<int32_t>(),
+                           fb.d_w_ptr.as<int64_t>(), fb.d_w_col.as<int32_t>(), fb.d_w_val.as<double>(),
+                           p.w_Y.as<double>(), p.w_D.as<double>(), bD);
         OSHT_HIP(hipGetLastError());
       }
-      gemm_tasks_launch(p, bt + t1, t2 - t1, "apply_forward_correction", st);
+      gemm_tasks_launch(p, bt + tp[1], tp[2] - tp[1], true, "apply_forward_correction", st);
     }
   }
   launch_fwd_scatter(p, p.w_Y.as<double>(), flm, B, st);

@@ -32,20 +32,64 @@ void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, cons
 
 namespace {
 
-// Inverse: X[slot][i][col] = coefficient (l0+i, m) of map b (sign-adjusted).
-__global__ __launch_bounds__(256) void inv_gather_kernel(Geo g, const Slot* __restrict__ slots, int slot0,
-                                                         const double* __restrict__ flm, double* __restrict__ X) {
-  const int slot = slot0 + blockIdx.y;
-  const Slot sl = slots[slot];
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = e / g.ncols, col = e % g.ncols;
-  if (i >= sl.K) return;
-  int sgn, b, part, m;
-  decode_col(g, sl, col, sgn, b, part, m);
-  const int l = sl.l0 + i;
-  double v = flm[((int64_t)b * g.L * g.L + (int64_t)l * l + l + m) * 2 + part];
-  if (g.s == 0 && sgn && (sl.m & 1)) v = -v;
-  X[((int64_t)slot * g.L + i) * g.ncols + col] = v;
+// Coefficients (l-major, map-major) <-> slot layout, through an LDS tile of
+// 64 consecutive orders x 16 maps per step: one workgroup per degree l.
+// to_slots: X[slot(m)][l - l0(m)][col(m, b)] = sign(m) * flm[b][l^2 + l + m]
+// else:     flm[b][l^2 + l + m] = sign(m) * Y[slot(m)][l - l0(m)][col(m, b)],
+//           zero when l < l0(m) (spin: degrees below |s|).
+// sign(m) = (-1)^|m| for spin 0 and m < 0 (both orders share A_|m|, Q_|m|).
+template <bool TO_SLOTS>
+__global__ __launch_bounds__(256) void coef_transpose_kernel(Geo g, const double2* __restrict__ src,
+                                                             double2* __restrict__ dst) {
+  __shared__ double2 tile[16][65];
+  const int l = blockIdx.x;
+  const int nc = g.ncols >> 1;
+  const int as = g.s < 0 ? -g.s : g.s;
+  const int64_t LL = (int64_t)g.L * g.L;
+  for (int m0 = -l; m0 <= l; m0 += 64) {
+    const int nm = min(64, l - m0 + 1);
+    for (int b0 = 0; b0 < g.B; b0 += 16) {
+      const int nb = min(16, g.B - b0);
+      if (TO_SLOTS) {
+        for (int e = threadIdx.x; e < nb * nm; e += blockDim.x) {
+          const int bb = e / nm, mi = e - bb * nm;
+          tile[bb][mi] = src[(int64_t)(b0 + bb) * LL + (int64_t)l * l + l + m0 + mi];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nm * nb; e += blockDim.x) {
+          const int mi = e / nb, bb = e - mi * nb;
+          const int m = m0 + mi, am = m < 0 ? -m : m;
+          const int l0 = am > as ? am : as;
+          if (l < l0) continue;
+          const int slot = g.s == 0 ? am : m + g.L - 1;
+          const int sgn = (g.s == 0 && m < 0) ? 1 : 0;
+          double2 v = tile[bb][mi];
+          if (sgn && (am & 1)) { v.x = -v.x; v.y = -v.y; }
+          dst[((int64_t)slot * g.L + (l - l0)) * nc + sgn * g.B + b0 + bb] = v;
+        }
+      } else {
+        for (int e = threadIdx.x; e < nm * nb; e += blockDim.x) {
+          const int mi = e / nb, bb = e - mi * nb;
+          const int m = m0 + mi, am = m < 0 ? -m : m;
+          const int l0 = am > as ? am : as;
+          double2 v = {0.0, 0.0};
+          if (l >= l0) {
+            const int slot = g.s == 0 ? am : m + g.L - 1;
+            const int sgn = (g.s == 0 && m < 0) ? 1 : 0;
+            v = src[((int64_t)slot * g.L + (l - l0)) * nc + sgn * g.B + b0 + bb];
+            if (sgn && (am & 1)) { v.x = -v.x; v.y = -v.y; }
+          }
+          tile[bb][mi] = v;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nb * nm; e += blockDim.x) {
+          const int bb = e / nm, mi = e - bb * nm;
+          dst[(int64_t)(b0 + bb) * LL + (int64_t)l * l + l + m0 + mi] = tile[bb][mi];
+        }
+      }
+      __syncthreads();
+    }
+  }
 }
 
 // Forward, one level: X[slot][r][col], ring k = |m| + r: bin minus aliases.
@@ -69,41 +113,6 @@ __global__ __launch_bounds__(256) void fwd_gather_kernel(Geo g, const Slot* __re
     v -= Y[alias_index(g, slots, mp, k, b, part)];
   }
   X[((int64_t)slot * g.L + r) * g.ncols + col] = v;
-}
-
-// Forward: flm[b][l^2 + l + m] from the coefficient rows of Y (pull form;
-// zeros for l < |s|).
-__global__ __launch_bounds__(256) void fwd_scatter_kernel(Geo g, const Slot* __restrict__ slots,
-                                                          const double* __restrict__ Y, double* __restrict__ flm,
-                                                          double sign_neg) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t LL = (int64_t)g.L * g.L;
-  if (e >= LL * g.B) return;
-  const int b = (int)(e / LL);
-  const int idx = (int)(e - (int64_t)b * LL);
-  const int l = (int)sqrt((double)idx);
-  int ll = l;
-  while ((int64_t)(ll + 1) * (ll + 1) <= idx) ++ll;
-  while ((int64_t)ll * ll > idx) --ll;
-  const int m = idx - ll * ll - ll;
-  double re = 0.0, im = 0.0;
-  int slot, col;
-  if (g.s == 0) {
-    slot = m < 0 ? -m : m;
-    col = (m < 0 ? 2 * g.B : 0) + 2 * b;
-  } else {
-    slot = m + g.L - 1;
-    col = 2 * b;
-  }
-  const Slot sl = slots[slot];
-  if (ll >= sl.l0) {
-    const double* y = Y + ((int64_t)slot * g.L + (ll - sl.l0)) * g.ncols + col;
-    re = y[0];
-    im = y[1];
-    if (g.s == 0 && m < 0 && (slot & 1)) { re *= sign_neg; im *= sign_neg; }
-  }
-  flm[e * 2] = re;
-  flm[e * 2 + 1] = im;
 }
 
 // Inverse adjoint: X[slot][k][col] = Hbar_k[m mod n_k] for every ring k.
@@ -160,8 +169,6 @@ __global__ __launch_bounds__(256) void fadj_scatter_kernel(Geo g, const Slot* __
   H[(((int64_t)k * k + pmod(m, n)) * g.B + b) * 2 + part] = Y[((int64_t)slot * g.L + r) * g.ncols + col];
 }
 
-// Inverse adjoint: flmbar from the K rows of Y (pull form; zeros for l < |s|).
-// Same addressing as fwd_scatter_kernel.
 
 }  // namespace
 
@@ -222,24 +229,23 @@ void ensure_workspace(Plan& p, int64_t B) {
   gemm_tasks(p.h_gdesc, p.h_gtask);
   upload(p.d_gdesc, p.h_gdesc);
   upload(p.d_gtask, p.h_gtask);
-  // per-block task lists of the blocked forward
+  // per-block task lists of the blocked forward: [Q apply, correction]
   std::vector<GemmTask> bt;
   p.h_btask_ptr.clear();
   const int nblk = (int)p.fb.q0.size();
+  auto emit = [&](int d) {
+    const GemmDesc& g = p.h_gdesc[d];
+    if (g.K <= 0 || g.M <= 0) return;
+    for (int a = 0; a < (int)ceil_div(g.M, 64); ++a)
+      for (int c = 0; c < (int)ceil_div(g.N, 64); ++c) bt.push_back(GemmTask{d, a, c, 0});
+  };
   for (int blk = 0; blk < nblk; ++blk) {
-    for (int pass = 0; pass < 2; ++pass) {
-      p.h_btask_ptr.push_back((int32_t)bt.size());
-      const int dir = pass == 0 ? kFwd : kCorr;
-      const bool has_unk = p.fb.unk_ptr[blk + 1] > p.fb.unk_ptr[blk];
-      if (pass == 1 && !has_unk) continue;
-      for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) {
-        const int d = dir * p.nslots + p.fb.slot_list[i];
-        const GemmDesc& g = p.h_gdesc[d];
-        if (g.K <= 0) continue;
-        for (int a = 0; a < (int)ceil_div(g.M, 64); ++a)
-          for (int c = 0; c < (int)ceil_div(g.N, 64); ++c) bt.push_back(GemmTask{d, a, c, 0});
-      }
-    }
+    const bool has_unk = p.fb.unk_ptr[blk + 1] > p.fb.unk_ptr[blk];
+    p.h_btask_ptr.push_back((int32_t)bt.size());
+    for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) emit(kFwd * p.nslots + p.fb.slot_list[i]);
+    p.h_btask_ptr.push_back((int32_t)bt.size());
+    if (has_unk)
+      for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) emit(kCorr * p.nslots + p.fb.slot_list[i]);
   }
   p.h_btask_ptr.push_back((int32_t)bt.size());
   upload(p.d_btask, bt);
@@ -248,16 +254,23 @@ void ensure_workspace(Plan& p, int64_t B) {
 
 void launch_fwd_scatter(const Plan& p, const double* Y, double* flm, int64_t B, hipStream_t st) {
   const Geo g = geo(p, B);
-  const int64_t tot = (int64_t)p.L * p.L * B;
-  hipLaunchKernelGGL(fwd_scatter_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, st, g, p.d_slots.as<Slot>(), Y,
-                     flm, -1.0);
+  hipLaunchKernelGGL(coef_transpose_kernel<false>, dim3(p.L), dim3(256), 0, st, g,
+                     reinterpret_cast<const double2*>(Y), reinterpret_cast<double2*>(flm));
   OSHT_HIP(hipGetLastError());
 }
 
-void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, const char* prof_name, hipStream_t st) {
+void launch_coef_to_slots(const Plan& p, const double* flm, double* X, int64_t B, hipStream_t st) {
+  const Geo g = geo(p, B);
+  hipLaunchKernelGGL(coef_transpose_kernel<true>, dim3(p.L), dim3(256), 0, st, g,
+                     reinterpret_cast<const double2*>(flm), reinterpret_cast<double2*>(X));
+  OSHT_HIP(hipGetLastError());
+}
+
+void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, bool a_rowfast, const char* prof_name,
+                       hipStream_t st) {
   if (count <= 0) return;
   ProfScope ps(p.prof, prof_name, st);
-  launch_gemm_f64(p.d_gdesc.as<GemmDesc>(), d_tasks, count, st);
+  launch_gemm_f64(p.d_gdesc.as<GemmDesc>(), d_tasks, count, a_rowfast, true, st);
 }
 
 namespace {
@@ -283,7 +296,9 @@ void task_range(const Plan& p, int dir, int s0, int s1, int& first, int& count) 
 void gemm_slots(Plan& p, int dir, int s0, int s1, hipStream_t st) {
   int first, count;
   task_range(p, dir, s0, s1, first, count);
-  gemm_tasks_launch(p, p.d_gtask.as<GemmTask>() + first, count, kApplyName[dir], st);
+  // inverse / forward read A or Q column-major; the adjoints read them transposed
+  gemm_tasks_launch(p, p.d_gtask.as<GemmTask>() + first, count, dir == kInv || dir == kFwd || dir == kCorr,
+                    kApplyName[dir], st);
 }
 
 // slots of level am: spin 0 -> [am, am+1); spin s -> {-am, +am}
@@ -299,9 +314,8 @@ void level_slots(const Plan& p, int am, int& s0, int& s1) {
 void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t st) {
   ensure_workspace(p, B);
   const Geo g = geo(p, B);
-  const dim3 grid((unsigned)ceil_div((int64_t)p.L * g.ncols, 256), (unsigned)p.nslots);
-  hipLaunchKernelGGL(inv_gather_kernel, grid, dim3(256), 0, st, g, p.d_slots.as<Slot>(), 0, flm, p.w_X.as<double>());
-  OSHT_HIP(hipGetLastError());
+  (void)g;
+  launch_coef_to_slots(p, flm, p.w_X.as<double>(), B, st);
   gemm_slots(p, kInv, 0, p.nslots, st);
   ProfScope ps(p.prof, "ring_synthesis", st);
   launch_ring_synthesis(p, nullptr, 0, p.w_Y.as<double>(), f, B, st);
@@ -334,10 +348,7 @@ void run_forward_levels(Plan& p, const double* f, double* flm, int64_t B, hipStr
       }
     }
   }
-  const int64_t tot = (int64_t)p.L * p.L * B;
-  hipLaunchKernelGGL(fwd_scatter_kernel, dim3((unsigned)ceil_div(tot, 256)), blk, 0, st, g, p.d_slots.as<Slot>(),
-                     p.w_Y.as<double>(), flm, -1.0);
-  OSHT_HIP(hipGetLastError());
+  launch_fwd_scatter(p, p.w_Y.as<double>(), flm, B, st);
 }
 
 void run_inverse_adjoint(Plan& p, const double* fbar, double* flmbar, int64_t B, hipStream_t st) {
@@ -349,10 +360,7 @@ void run_inverse_adjoint(Plan& p, const double* fbar, double* flmbar, int64_t B,
                      p.w_X.as<double>());
   OSHT_HIP(hipGetLastError());
   gemm_slots(p, kIadj, 0, p.nslots, st);
-  const int64_t tot = (int64_t)p.L * p.L * B;
-  hipLaunchKernelGGL(fwd_scatter_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, st, g, p.d_slots.as<Slot>(),
-                     p.w_Y.as<double>(), flmbar, -1.0);
-  OSHT_HIP(hipGetLastError());
+  launch_fwd_scatter(p, p.w_Y.as<double>(), flmbar, B, st);
 }
 
 void run_forward_adjoint(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st) {

@@ -42,7 +42,9 @@ __device__ __forceinline__ int64_t alias_index(const Geo& g, const Slot* __restr
     slot = mp + g.L - 1;
     col = 2 * b + part;
   }
-  const int K = slots[slot].K;
+  const int amp = mp < 0 ? -mp : mp;
+  const int K = g.L - (amp > (g.s < 0 ? -g.s : g.s) ? amp : (g.s < 0 ? -g.s : g.s));  // L - max(|m'|, |s|)
+  (void)slots;
   return ((int64_t)slot * g.L + K + k) * g.ncols + col;
 }
 
@@ -51,7 +53,8 @@ enum { kInv = 0, kFwd = 1, kIadj = 2, kFadj = 3, kCorr = 4, kNumDir = 5 };
 
 void ensure_workspace(Plan& p, int64_t B);
 void launch_fwd_scatter(const Plan& p, const double* Y, double* flm, int64_t B, hipStream_t st);
-void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, const char* prof_name, hipStream_t st);
+void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, bool a_rowfast, const char* prof_name,
+                       hipStream_t st);
 
 inline Geo geo(const Plan& p, int64_t B) { return Geo{p.L, p.spin, (int)B, (int)(p.ncols_per_map * B)}; }
 
