@@ -428,7 +428,8 @@ void build_plan(Plan& p) {
   if (const char* env = std::getenv("OSHT_FWD_BLOCK")) b = std::max(1, std::atoi(env));
   for (;;) {
     build_fwd_blocks(p, b);
-    const size_t need = sizeof(double) * ((size_t)p.fb.max_unk * p.fb.cpw + p.fb.max_w) + sizeof(int32_t) * p.fb.max_w;
+    const size_t need = sizeof(double) * ((size_t)p.fb.max_unk * p.fb.cpw + p.fb.max_w) +
+                        sizeof(int32_t) * (p.fb.max_w + p.fb.max_unk + 1);
     if (need <= (size_t)p.fb.lds_limit || b == 1) break;
     b = std::max(1, b * 3 / 4);
   }

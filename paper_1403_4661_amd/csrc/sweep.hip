@@ -87,12 +87,14 @@ __global__ __launch_bounds__(512) void delta_solve_kernel(Geo g, int u0, int nu,
   double* dl = lds;                                   // nu * cpw
   double* wv = lds + (size_t)nu * cpw;                // nw
   int32_t* wc = reinterpret_cast<int32_t*>(wv + nw);  // nw
+  int32_t* wp = wc + nw;                              // nu + 1 (block-relative row starts)
   const int j0 = blockIdx.x * cpw;
   const int J = 2 * g.B;
   for (int i = threadIdx.x; i < nw; i += blockDim.x) {
     wv[i] = w_val[wbase + i];
     wc[i] = w_col[wbase + i];
   }
+  for (int i = threadIdx.x; i <= nu; i += blockDim.x) wp[i] = (int32_t)(w_ptr[u0 + i] - wbase);
   // beta for every unknown and column of this group
   for (int e = threadIdx.x; e < nu * cpw; e += blockDim.x) {
     const int ul = e / cpw, jj = e - ul * cpw, j = j0 + jj;
@@ -105,18 +107,23 @@ __global__ __launch_bounds__(512) void delta_solve_kernel(Geo g, int u0, int nu,
     dl[e] = acc;
   }
   __syncthreads();
+  // level-ordered substitution, LDS only
   for (int lv = 0; lv < nlev; ++lv) {
     const int a = lev_ptr[lv] - u0, b = lev_ptr[lv + 1] - u0;
     for (int e = threadIdx.x; e < (b - a) * cpw; e += blockDim.x) {
-      const int ul = a + e / cpw, jj = e % cpw, j = j0 + jj;
-      const int u = u0 + ul;
+      const int ul = a + e / cpw, jj = e % cpw;
       double acc = dl[ul * cpw + jj];
-      const int w1 = (int)(w_ptr[u + 1] - wbase);
-      for (int w = (int)(w_ptr[u] - wbase); w < w1; ++w) acc -= wv[w] * dl[wc[w] * cpw + jj];
+      for (int w = wp[ul]; w < wp[ul + 1]; ++w) acc -= wv[w] * dl[wc[w] * cpw + jj];
       dl[ul * cpw + jj] = acc;
-      if (j < J) D[((int64_t)unk_slot[u] * bD + unk_r[u]) * g.ncols + order_col(g, unk_m[u], j)] = acc;
     }
     __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nu * cpw; e += blockDim.x) {
+    const int ul = e / cpw, jj = e - ul * cpw, j = j0 + jj;
+    if (j < J) {
+      const int u = u0 + ul;
+      D[((int64_t)unk_slot[u] * bD + unk_r[u]) * g.ncols + order_col(g, unk_m[u], j)] = dl[e];
+    }
   }
 }
 
@@ -280,7 +287,7 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
       const int lv0 = fb.lev_blk_ptr[blk], lv1 = fb.lev_blk_ptr[blk + 1];
       const int64_t nw = fb.w_ptr[u0 + nu] - fb.w_ptr[u0];
       const int cpw = fb.cpw;
-      const size_t lds = sizeof(double) * ((size_t)nu * cpw + nw) + sizeof(int32_t) * nw;
+      const size_t lds = sizeof(double) * ((size_t)nu * cpw + nw) + sizeof(int32_t) * (nw + nu + 1);
       {
         ProfScope ps(p.prof, "delta_solve", st);
         hipLaunchKernelGGL(delta_solve_kernel, dim3((unsigned)ceil_div(2 * B, cpw)), dim3(512), lds, st, g, u0, nu,
