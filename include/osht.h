@@ -46,8 +46,15 @@ extern "C" {
 #define OSHT_EIO          -6  /* placement cache file unreadable or malformed */
 
 /* ------------------------------------------------------------------ flags */
-/* arithmetic of the order-wise apply */
+/* arithmetic of the order-wise apply (Procedure 1 step solve and alias
+ * evaluation, Procedure 2 step evaluation, and their adjoints).  The
+ * Legendre/Wigner recursion, the inversion of every P_m, the ring DFTs, the
+ * alias gathers and every buffer the caller sees stay FP64 in all modes. */
 #define OSHT_PREC_FP64        0x0u   /* FP64 throughout */
+#define OSHT_PREC_FP32        0x1u   /* matrices A_m and [P_m^-1; A_m^top P_m^-1] built in FP64,
+                                        then stored rounded to FP32; applied on FP32 matrix cores
+                                        with FP32 accumulation over 16-term k-slices summed in FP64;
+                                        the RHS is rounded to FP32 as it is staged */
 #define OSHT_PREC_MASK        0x0fu
 /* colatitude placement (Sec. III-D) */
 #define OSHT_THETA_GREEDY       0x00u  /* condition-number-minimising greedy */

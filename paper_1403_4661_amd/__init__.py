@@ -46,14 +46,19 @@ def theta_alternating(L):
 class Plan:
     """A transform plan for band-limit L and spin s on the current device."""
 
-    def __init__(self, L, spin=0, placement="greedy", theta_cache_dir=THETA_CACHE_DIR, device=None):
+    def __init__(self, L, spin=0, placement="greedy", precision="fp64", theta_cache_dir=THETA_CACHE_DIR,
+                 device=None):
+        """precision: "fp64" (FP64 throughout) or "fp32" (order-wise applies on
+        FP32-stored matrices with FP32 matrix cores; everything else FP64)."""
         import torch
 
         if placement not in ("greedy", "alternating"):
             raise ValueError("placement must be 'greedy' or 'alternating'")
-        flags = _lib.OSHT_PREC_FP64 | (
+        if precision not in ("fp64", "fp32"):
+            raise ValueError("precision must be 'fp64' or 'fp32'")
+        flags = (_lib.OSHT_PREC_FP64 if precision == "fp64" else _lib.OSHT_PREC_FP32) | (
             _lib.OSHT_THETA_GREEDY if placement == "greedy" else _lib.OSHT_THETA_ALTERNATING)
-        self.L, self.spin = int(L), int(spin)
+        self.L, self.spin, self.precision = int(L), int(spin), precision
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._h = ctypes.c_void_p()
         d = theta_cache_dir.encode() if theta_cache_dir else None

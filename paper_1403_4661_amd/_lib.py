@@ -20,6 +20,7 @@ OSHT_ENOTSUP = -5
 OSHT_EIO = -6
 
 OSHT_PREC_FP64 = 0x0
+OSHT_PREC_FP32 = 0x1
 OSHT_THETA_GREEDY = 0x00
 OSHT_THETA_ALTERNATING = 0x10
 

@@ -155,7 +155,8 @@ int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_di
   if (L < 1 || L > 4096) return fail(OSHT_EINVAL, "L must be in [1, 4096]");
   if (spin <= -L || spin >= L) return fail(OSHT_EINVAL, "|spin| must be < L");
   const uint32_t prec = flags & OSHT_PREC_MASK, theta = flags & OSHT_THETA_MASK;
-  if (prec != OSHT_PREC_FP64) return fail(OSHT_ENOTSUP, "only OSHT_PREC_FP64 is available");
+  if (prec != OSHT_PREC_FP64 && prec != OSHT_PREC_FP32)
+    return fail(OSHT_ENOTSUP, "precision must be OSHT_PREC_FP64 or OSHT_PREC_FP32");
   if (theta != OSHT_THETA_GREEDY && theta != OSHT_THETA_ALTERNATING) return fail(OSHT_EINVAL, "unknown placement flag");
   if (flags & ~(OSHT_PREC_MASK | OSHT_THETA_MASK)) return fail(OSHT_EINVAL, "unknown flag bits");
   osht_plan_t* h = nullptr;
@@ -165,6 +166,7 @@ int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_di
     p.L = L;
     p.spin = spin;
     p.flags = flags;
+    p.fp32 = prec == OSHT_PREC_FP32;
     OSHT_HIP(hipGetDevice(&p.device));
     p.numer.assign(L, 0);
     if (theta == OSHT_THETA_ALTERNATING) {

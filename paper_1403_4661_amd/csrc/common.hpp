@@ -84,7 +84,8 @@ struct Slot {
 // Batched GEMM descriptor: C(MxN) = alpha * A(MxK) * B(KxN) + beta * C,
 // element (i, j) of X at X[i * sXr + j * sXc].
 struct GemmDesc {
-  const double* A;
+  const void* A;  // double, or float for FP32-matrix plans
+
   const double* B;
   double* C;
   int64_t sAr, sAc, sBr, sBc, sCr, sCc;
@@ -135,20 +136,22 @@ struct FwdBlocks {
   std::vector<int64_t> w_ptr;                  // per unknown -> W entries
   std::vector<int32_t> w_col;                  // block-local unknown index
   std::vector<int64_t> w_idx;                  // element of d_Q holding the value
+  int kthr = 0;                                // rings k < kthr: wide gather
+  std::vector<int32_t> wide_ptr, wide_slot, wide_row;  // block -> (slot, row) pairs of rings k < kthr
   int max_unk = 0;
   int64_t max_w = 0;                           // max W entries in one block
   int cpw = 8;                                 // delta-solve columns per workgroup
   int lds_limit = 160 * 1024;
   void clear_host() {
     for (auto* v : {&q0, &q1, &slot_ptr, &slot_list, &unk_ptr, &lev_blk_ptr, &lev_ptr, &unk_slot, &unk_r, &unk_m,
-                    &src_ptr, &src_slot, &src_row, &src_m, &w_col})
+                    &src_ptr, &src_slot, &src_row, &src_m, &w_col, &wide_ptr, &wide_slot, &wide_row})
       v->clear();
     w_ptr.clear();
     w_idx.clear();
     max_unk = 0;
   }
   DevBuf d_slot_list, d_lev_ptr, d_unk_slot, d_unk_r, d_unk_m, d_src_ptr, d_src_slot, d_src_row, d_src_m,
-      d_w_ptr, d_w_col, d_w_val;
+      d_w_ptr, d_w_col, d_w_val, d_wide_slot, d_wide_row;
 };
 
 struct Plan {
@@ -163,7 +166,9 @@ struct Plan {
   // device memory
   DevBuf d_cos, d_sin, d_cosh, d_sinh;
   DevBuf d_slots;
-  DevBuf d_A, d_Q;            // FP64 blocks
+  DevBuf d_A, d_Q;            // FP64 blocks (released after the FP32 copies are made for FP32 plans)
+  DevBuf d_A32, d_Q32;        // FP32 copies, same offsets (FP32 plans)
+  bool fp32 = false;          // order-wise applies on FP32 matrices
   DevBuf d_rings, d_chirp, d_twiddle, d_chirp_tab;
   std::vector<int32_t> h_ring_logM;
   int max_logM = 0;
@@ -210,12 +215,10 @@ void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t s
 void run_inverse_adjoint(Plan& p, const double* fbar, double* flmbar, int64_t B, hipStream_t st);
 void run_forward_adjoint(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st);
 
-// GEMM (gemm.hip): tasks and descriptors already on the device.  All
-// descriptors of one launch share the operand layout: a_rowfast <=> sAr == 1
-// (A column-major), b_colfast <=> sBc == 1 (B row-major); other strides are
-// taken from each descriptor.
-void launch_gemm_f64(const GemmDesc* d_desc, const GemmTask* d_task, int ntask, bool a_rowfast, bool b_colfast,
-                     hipStream_t st);
+// GEMM (gemm.hip): tasks and descriptors already on the device.
+enum class GemmRole { Plan, ApplyInverse, ApplyForward, Correction, Adjoint };
+void launch_gemm(GemmRole role, bool fp32_matrix, const GemmDesc* d_desc, const GemmTask* d_task, int ntask,
+                 hipStream_t st);
 // Builds tasks for descriptors (64 x 64 tiles).
 void gemm_tasks(const std::vector<GemmDesc>& descs, std::vector<GemmTask>& tasks);
 

@@ -293,13 +293,13 @@ double newton_schulz(Plan& p, int s0, int s1, DevBuf& scratch, std::vector<doubl
   double best = INFINITY, last = INFINITY;
   int stall = 0;
   for (int it = 0; it < 120; ++it) {
-    launch_gemm_f64(gPX.as<GemmDesc>(), kPX.as<GemmTask>(), (int)tPX.size(), true, false, 0);
+    launch_gemm(GemmRole::Plan, false, gPX.as<GemmDesc>(), kPX.as<GemmTask>(), (int)tPX.size(), 0);
     hipLaunchKernelGGL(ns_copy_kernel, dim3(64, ns), dim3(256), 0, 0, d_slots, s0, Q, scr, d_offXn.as<int64_t>(), 2.0, 0);
-    launch_gemm_f64(gXT.as<GemmDesc>(), kXT.as<GemmTask>(), (int)tXT.size(), true, false, 0);
+    launch_gemm(GemmRole::Plan, false, gXT.as<GemmDesc>(), kXT.as<GemmTask>(), (int)tXT.size(), 0);
     hipLaunchKernelGGL(ns_copy_kernel, dim3(64, ns), dim3(256), 0, 0, d_slots, s0, Q, scr, d_offXn.as<int64_t>(), 1.0, 1);
     OSHT_HIP(hipGetLastError());
     if (it < 8) continue;
-    launch_gemm_f64(gXP.as<GemmDesc>(), kXP.as<GemmTask>(), (int)tXP.size(), true, false, 0);
+    launch_gemm(GemmRole::Plan, false, gXP.as<GemmDesc>(), kXP.as<GemmTask>(), (int)tXP.size(), 0);
     hipLaunchKernelGGL(ns_resid_kernel, dim3(ns), dim3(256), 0, 0, d_slots, s0, scr, d_offE.as<int64_t>(), d_out.as<double>());
     OSHT_HIP(hipGetLastError());
     OSHT_HIP(hipMemcpy(res.data(), d_out.p, sizeof(double) * ns, hipMemcpyDeviceToHost));
@@ -320,12 +320,23 @@ double newton_schulz(Plan& p, int s0, int s1, DevBuf& scratch, std::vector<doubl
   return best;
 }
 
+// round-to-nearest FP32 copy
+__global__ void narrow_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
 }  // namespace
 
 int64_t Plan::device_bytes() const {
-  return (int64_t)(d_cos.bytes + d_sin.bytes + d_cosh.bytes + d_sinh.bytes + d_slots.bytes + d_A.bytes + d_Q.bytes +
-                   d_rings.bytes + d_chirp.bytes + d_twiddle.bytes + d_chirp_tab.bytes + w_X.bytes + w_Y.bytes + w_H.bytes + w_T.bytes +
-                   d_gdesc.bytes + d_gtask.bytes);
+  size_t n = 0;
+  for (const DevBuf* b : {&d_cos, &d_sin, &d_cosh, &d_sinh, &d_slots, &d_A, &d_Q, &d_A32, &d_Q32, &d_rings, &d_chirp,
+                          &d_twiddle, &d_chirp_tab, &w_X, &w_Y, &w_H, &w_T, &w_D, &d_gdesc, &d_gtask, &d_btask,
+                          &fb.d_slot_list, &fb.d_lev_ptr, &fb.d_unk_slot, &fb.d_unk_r, &fb.d_unk_m, &fb.d_src_ptr,
+                          &fb.d_src_slot, &fb.d_src_row, &fb.d_src_m, &fb.d_w_ptr, &fb.d_w_col, &fb.d_w_val,
+                          &fb.d_wide_slot, &fb.d_wide_row})
+    n += b->bytes;
+  return (int64_t)n;
 }
 
 void build_plan(Plan& p) {
@@ -418,7 +429,7 @@ void build_plan(Plan& p) {
     DevBuf gd, gt;
     upload(gd, dC);
     upload(gt, tC);
-    launch_gemm_f64(gd.as<GemmDesc>(), gt.as<GemmTask>(), (int)tC.size(), true, false, 0);
+    launch_gemm(GemmRole::Plan, false, gd.as<GemmDesc>(), gt.as<GemmTask>(), (int)tC.size(), 0);
     OSHT_HIP(hipDeviceSynchronize());
   }
   build_chirps(p);
@@ -432,6 +443,20 @@ void build_plan(Plan& p) {
                         sizeof(int32_t) * (p.fb.max_w + p.fb.max_unk + 1);
     if (need <= (size_t)p.fb.lds_limit || b == 1) break;
     b = std::max(1, b * 3 / 4);
+  }
+  if (p.fp32) {
+    // FP32 copies at the same element offsets; the FP64 blocks are released
+    auto narrow = [](DevBuf& src, DevBuf& dst) {
+      const int64_t n = (int64_t)(src.bytes / sizeof(double));
+      dst.alloc(sizeof(float) * std::max<int64_t>(n, 1));
+      hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(n, 256), 1), 8192)),
+                         dim3(256), 0, 0, src.as<double>(), dst.as<float>(), n);
+      OSHT_HIP(hipGetLastError());
+      OSHT_HIP(hipDeviceSynchronize());
+      src.release();
+    };
+    narrow(p.d_A, p.d_A32);
+    narrow(p.d_Q, p.d_Q32);
   }
   OSHT_HIP(hipDeviceSynchronize());
 }

@@ -31,7 +31,7 @@ namespace {
 // One thread per (row r, complex column cc = sgn * B + b): both doubles of
 // the complex RHS entry, with the alias search shared by re and im.
 __global__ __launch_bounds__(256) void block_gather_kernel(Geo g, const Slot* __restrict__ slots,
-                                                           const int32_t* __restrict__ slot_list, int q1,
+                                                           const int32_t* __restrict__ slot_list, int q1, int kthr,
                                                            const double2* __restrict__ H, const double* __restrict__ Y,
                                                            double2* __restrict__ X) {
   const int slot = slot_list[blockIdx.y];
@@ -45,6 +45,7 @@ __global__ __launch_bounds__(256) void block_gather_kernel(Geo g, const Slot* __
   const int m = sgn ? -sl.m : sl.m;
   const int am = m < 0 ? -m : m;
   const int k = am + r, n = 2 * k + 1;
+  if (k < kthr) return;  // many aliases: wide_gather_kernel
   const int bin = pmod(m, n);
   double2 v = H[((int64_t)k * k + bin) * g.B + b];
   const int start = bin - ((bin + g.L - 1) / n) * n;
@@ -56,6 +57,56 @@ __global__ __launch_bounds__(256) void block_gather_kernel(Geo g, const Slot* __
     v.y -= a.y;
   }
   X[((int64_t)slot * g.L + r) * nc + cc] = v;
+}
+
+// The rows of small rings (k < kthr) alias ~(2L-1)/n_k solved orders each.
+// One workgroup per (slot, row): threads split the columns and, for each
+// column, the alias list into C interleaved chunks whose partial sums are
+// reduced in a fixed order through LDS.
+__global__ __launch_bounds__(256) void wide_gather_kernel(Geo g, const Slot* __restrict__ slots,
+                                                          const int32_t* __restrict__ wide_slot,
+                                                          const int32_t* __restrict__ wide_row, int q1,
+                                                          const double2* __restrict__ H, const double* __restrict__ Y,
+                                                          double2* __restrict__ X) {
+  __shared__ double2 part[256];
+  const int slot = wide_slot[blockIdx.x], r = wide_row[blockIdx.x];
+  const Slot sl = slots[slot];
+  const int nc = g.ncols >> 1;
+  const int cw = nc < 256 ? nc : 256;  // columns in flight
+  const int C = 256 / cw;              // alias chunks per column
+  const int ci = threadIdx.x % cw, chunk = threadIdx.x / cw;
+  for (int cc0 = 0; cc0 < nc; cc0 += cw) {
+    const int cc = cc0 + ci;
+    double2 acc = {0.0, 0.0};
+    int bin = 0, m = 0, k = 0, b = 0;
+    if (chunk < C && cc < nc) {
+      const int sgn = (g.s == 0) ? cc / g.B : 0;
+      b = cc - sgn * g.B;
+      m = sgn ? -sl.m : sl.m;
+      k = (m < 0 ? -m : m) + r;
+      const int n = 2 * k + 1;
+      bin = pmod(m, n);
+      const int start = bin - ((bin + g.L - 1) / n) * n;
+      for (int mp = start + chunk * n; mp <= g.L - 1; mp += C * n) {
+        const int amp = mp < 0 ? -mp : mp;
+        if (mp == m || amp < q1) continue;
+        const double2 a = *reinterpret_cast<const double2*>(Y + alias_index(g, slots, mp, k, b, 0));
+        acc.x += a.x;
+        acc.y += a.y;
+      }
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (chunk == 0 && cc < nc) {
+      double2 v = H[((int64_t)k * k + bin) * g.B + b];
+      for (int c = 0; c < C; ++c) {
+        v.x -= part[c * cw + ci].x;
+        v.y -= part[c * cw + ci].y;
+      }
+      X[((int64_t)slot * g.L + r) * nc + cc] = v;
+    }
+    __syncthreads();
+  }
 }
 
 __device__ __forceinline__ int order_col(const Geo& g, int m, int j) {
@@ -158,6 +209,10 @@ void build_fwd_blocks(Plan& p, int b) {
   fb.lev_blk_ptr.push_back(0);
   fb.src_ptr.push_back(0);
   fb.w_ptr.push_back(0);
+  fb.wide_ptr.push_back(0);
+  // rings with more than ~64 aliased orders per bin: n_k * 64 < 2L - 1
+  fb.kthr = 0;
+  while ((2 * fb.kthr + 1) * 64 < 2 * L - 1) ++fb.kthr;
   for (int q1 = L; q1 > 0; q1 -= fb.b) {
     const int q0 = std::max(0, q1 - fb.b);
     fb.q0.push_back(q0);
@@ -221,6 +276,16 @@ void build_fwd_blocks(Plan& p, int b) {
     }
     fb.unk_ptr.push_back((int32_t)fb.unk_m.size());
     fb.max_unk = std::max(fb.max_unk, (int)unks.size());
+    // rows of small rings gathered by the wide kernel
+    for (int i = fb.slot_ptr[fb.slot_ptr.size() - 2]; i < fb.slot_ptr.back(); ++i) {
+      const int sp = fb.slot_list[i];
+      const int am = std::abs(p.slots[sp].m);
+      for (int k = am; k < std::min(fb.kthr, L); ++k) {
+        fb.wide_slot.push_back(sp);
+        fb.wide_row.push_back(k - am);
+      }
+    }
+    fb.wide_ptr.push_back((int32_t)fb.wide_slot.size());
   }
   put_vec(fb.d_slot_list, fb.slot_list);
   put_vec(fb.d_lev_ptr, fb.lev_ptr);
@@ -233,6 +298,8 @@ void build_fwd_blocks(Plan& p, int b) {
   put_vec(fb.d_src_m, fb.src_m);
   put_vec(fb.d_w_ptr, fb.w_ptr);
   put_vec(fb.d_w_col, fb.w_col);
+  put_vec(fb.d_wide_slot, fb.wide_slot);
+  put_vec(fb.d_wide_row, fb.wide_row);
   const int64_t nw = (int64_t)fb.w_idx.size();
   fb.d_w_val.alloc(std::max<int64_t>(nw, 1) * sizeof(double));
   if (nw > 0) {
@@ -276,12 +343,20 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
       ProfScope ps(p.prof, "gather_forward", st);
       hipLaunchKernelGGL(block_gather_kernel, dim3((unsigned)ceil_div((int64_t)p.L * (g.ncols / 2), 256), ns), dim3(256),
                          0, st, g, p.d_slots.as<Slot>(), fb.d_slot_list.as<int32_t>() + fb.slot_ptr[blk], fb.q1[blk],
-                         reinterpret_cast<const double2*>(p.w_H.as<double>()), p.w_Y.as<double>(),
+                         fb.kthr, reinterpret_cast<const double2*>(p.w_H.as<double>()), p.w_Y.as<double>(),
                          reinterpret_cast<double2*>(p.w_X.as<double>()));
       OSHT_HIP(hipGetLastError());
+      const int nwide = fb.wide_ptr[blk + 1] - fb.wide_ptr[blk];
+      if (nwide > 0) {
+        hipLaunchKernelGGL(wide_gather_kernel, dim3((unsigned)nwide), dim3(256), 0, st, g, p.d_slots.as<Slot>(),
+                           fb.d_wide_slot.as<int32_t>() + fb.wide_ptr[blk], fb.d_wide_row.as<int32_t>() + fb.wide_ptr[blk],
+                           fb.q1[blk], reinterpret_cast<const double2*>(p.w_H.as<double>()), p.w_Y.as<double>(),
+                           reinterpret_cast<double2*>(p.w_X.as<double>()));
+        OSHT_HIP(hipGetLastError());
+      }
     }
     const int* tp = &p.h_btask_ptr[2 * blk];
-    gemm_tasks_launch(p, bt + tp[0], tp[1] - tp[0], true, "apply_forward", st);
+    gemm_tasks_launch(p, bt + tp[0], tp[1] - tp[0], GemmRole::ApplyForward, "apply_forward", st);
     const int u0 = fb.unk_ptr[blk], nu = fb.unk_ptr[blk + 1] - u0;
     if (nu > 0) {
       const int lv0 = fb.lev_blk_ptr[blk], lv1 = fb.lev_blk_ptr[blk + 1];
@@ -298,7 +373,7 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
                            p.w_Y.as<double>(), p.w_D.as<double>(), bD);
         OSHT_HIP(hipGetLastError());
       }
-      gemm_tasks_launch(p, bt + tp[1], tp[2] - tp[1], true, "apply_forward_correction", st);
+      gemm_tasks_launch(p, bt + tp[1], tp[2] - tp[1], GemmRole::Correction, "apply_forward_correction", st);
     }
   }
   launch_fwd_scatter(p, p.w_Y.as<double>(), flm, B, st);

@@ -195,8 +195,10 @@ void ensure_workspace(Plan& p, int64_t B) {
   double* X = p.w_X.as<double>();
   double* Y = p.w_Y.as<double>();
   double* D = p.w_D.as<double>();
-  const double* A = p.d_A.as<double>();
-  const double* Q = p.d_Q.as<double>();
+  // matrix element offsets are the same in the FP64 and FP32 copies
+  const char* A = static_cast<const char*>(p.fp32 ? p.d_A32.p : p.d_A.p);
+  const char* Q = static_cast<const char*>(p.fp32 ? p.d_Q32.p : p.d_Q.p);
+  const size_t es = p.fp32 ? sizeof(float) : sizeof(double);
   const int bD = std::max(p.fb.b, 1);
   std::vector<int32_t> wcorr(p.nslots, 0);  // correction width per slot
   for (size_t blk = 0; blk + 1 < p.fb.slot_ptr.size(); ++blk)
@@ -214,12 +216,12 @@ void ensure_workspace(Plan& p, int64_t B) {
       d.B = Xs; d.sBr = ncols; d.sBc = 1;
       d.C = Ys; d.sCr = ncols; d.sCc = 1;
       d.N = (int)ncols; d.alpha = 1.0; d.beta = 0.0;
-      if (dir == kInv) { d.A = A + sl.offA; d.sAr = 1; d.sAc = sl.ldA; d.M = p.L; d.K = sl.K; }
-      if (dir == kFwd) { d.A = Q + sl.offQ; d.sAr = 1; d.sAc = sl.ldQ; d.M = sl.K + am; d.K = sl.R; }
-      if (dir == kIadj) { d.A = A + sl.offA; d.sAr = sl.ldA; d.sAc = 1; d.M = sl.K; d.K = p.L; }
-      if (dir == kFadj) { d.A = Q + sl.offQ; d.sAr = sl.ldQ; d.sAc = 1; d.M = sl.R; d.K = sl.K + am; }
+      if (dir == kInv) { d.A = A + es * sl.offA; d.sAr = 1; d.sAc = sl.ldA; d.M = p.L; d.K = sl.K; }
+      if (dir == kFwd) { d.A = Q + es * sl.offQ; d.sAr = 1; d.sAc = sl.ldQ; d.M = sl.K + am; d.K = sl.R; }
+      if (dir == kIadj) { d.A = A + es * sl.offA; d.sAr = sl.ldA; d.sAc = 1; d.M = sl.K; d.K = p.L; }
+      if (dir == kFadj) { d.A = Q + es * sl.offQ; d.sAr = sl.ldQ; d.sAc = 1; d.M = sl.R; d.K = sl.K + am; }
       if (dir == kCorr) {  // Y -= Q[:, 0:w] D
-        d.A = Q + sl.offQ; d.sAr = 1; d.sAc = sl.ldQ; d.M = sl.K + am; d.K = std::min(wcorr[i], sl.R);
+        d.A = Q + es * sl.offQ; d.sAr = 1; d.sAc = sl.ldQ; d.M = sl.K + am; d.K = std::min(wcorr[i], sl.R);
         d.B = D + (int64_t)i * bD * ncols;
         d.alpha = -1.0; d.beta = 1.0;
       }
@@ -266,11 +268,11 @@ void launch_coef_to_slots(const Plan& p, const double* flm, double* X, int64_t B
   OSHT_HIP(hipGetLastError());
 }
 
-void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, bool a_rowfast, const char* prof_name,
+void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, GemmRole role, const char* prof_name,
                        hipStream_t st) {
   if (count <= 0) return;
   ProfScope ps(p.prof, prof_name, st);
-  launch_gemm_f64(p.d_gdesc.as<GemmDesc>(), d_tasks, count, a_rowfast, true, st);
+  launch_gemm(role, p.fp32, p.d_gdesc.as<GemmDesc>(), d_tasks, count, st);
 }
 
 namespace {
@@ -297,8 +299,11 @@ void gemm_slots(Plan& p, int dir, int s0, int s1, hipStream_t st) {
   int first, count;
   task_range(p, dir, s0, s1, first, count);
   // inverse / forward read A or Q column-major; the adjoints read them transposed
-  gemm_tasks_launch(p, p.d_gtask.as<GemmTask>() + first, count, dir == kInv || dir == kFwd || dir == kCorr,
-                    kApplyName[dir], st);
+  const GemmRole role = dir == kInv    ? GemmRole::ApplyInverse
+                        : dir == kFwd  ? GemmRole::ApplyForward
+                        : dir == kCorr ? GemmRole::Correction
+                                       : GemmRole::Adjoint;
+  gemm_tasks_launch(p, p.d_gtask.as<GemmTask>() + first, count, role, kApplyName[dir], st);
 }
 
 // slots of level am: spin 0 -> [am, am+1); spin s -> {-am, +am}

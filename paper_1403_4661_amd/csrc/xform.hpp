@@ -53,7 +53,7 @@ enum { kInv = 0, kFwd = 1, kIadj = 2, kFadj = 3, kCorr = 4, kNumDir = 5 };
 
 void ensure_workspace(Plan& p, int64_t B);
 void launch_fwd_scatter(const Plan& p, const double* Y, double* flm, int64_t B, hipStream_t st);
-void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, bool a_rowfast, const char* prof_name,
+void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, GemmRole role, const char* prof_name,
                        hipStream_t st);
 
 inline Geo geo(const Plan& p, int64_t B) { return Geo{p.L, p.spin, (int)B, (int)(p.ncols_per_map * B)}; }
