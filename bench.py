@@ -2,14 +2,23 @@
 
 One step = one inverse SHT followed by one forward SHT of a batch of B maps
 (the forward consumes the inverse's samples), on the headline workload:
-spin 0, L = 1024, B = 16, coefficients N(0,1)(1+l)^-1 (seed 5), FP64 path.
+spin 0, L = 1024, B = 16, coefficients N(0,1)(1+l)^-1 (seed 5).
 
-Prints one JSON line (the driver's contract) with, in addition:
-  roofline      the order-wise apply GEMM that dominates the step: algorithmic
-                FP64 flops (2 x matrix entries x 2B real columns per signed
-                order, summed over the launches timed live with HIP events in
-                the timed region) over its measured time, against the MI355X
-                FP64 matrix peak;
+Two paths run on the same inputs, each timed over its own K steps:
+  mixed  FP32 plan: FP32 matrix-core applies of A_m and P_m^{-1}; the alias
+         rows of the forward sweep, ring DFTs and all buffers FP64;
+  fp64   FP64 throughout.
+`value` is the mixed path's SHT/s; the fp64 path, the speedup and the
+errors of both paths are reported beside it.
+
+Prints one JSON line with, in addition:
+  roofline      the kernel that takes most of the step's time among the
+                order-wise apply GEMMs (the forward apply): algorithmic flops
+                (8 B x matrix entries per signed-order pair, summed over the
+                launches) over its duration measured live with HIP events
+                recorded on the library's stream around each of its launches
+                in the timed region, against the MI355X matrix peak of the
+                path's precision;
   cpu_baseline  the FP64 CPU oracle (tests' reference implementation) timed on
                 the host on a bounded sample (see 'sample'), scaled to the
                 metric's unit.
@@ -17,7 +26,6 @@ Prints one JSON line (the driver's contract) with, in addition:
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -25,8 +33,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6
-PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}  # MI355X dense matrix FP64 / FP32
 
 
 def parse():
@@ -37,7 +44,26 @@ def parse():
     ap.add_argument("--L", type=int, default=1024)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--paths", default="mixed,fp64", help="comma list; the first is the headline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device copy three times (HBM counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain copy kernel of known size: 2^30 bytes read and written per
+    launch.  rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE over this run gives the
+    counters' reading for a known number of HBM bytes."""
+    import torch
+
+    n = (1 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n * 8, "launches": 3}), flush=True)
 
 
 def cpu_baseline(L_metric):
@@ -77,10 +103,42 @@ def cpu_baseline(L_metric):
     }
 
 
+def forward_apply_flops(L, B):
+    """Algorithmic flops of the forward apply: order |m| streams the
+    L x (L-|m|) matrix [P^-1; A^top P^-1] against 4B real columns (spin 0
+    pairs +-m), 2 flops per entry and column."""
+    return sum(8.0 * B * L * (L - am) for am in range(L))
+
+
+def run_path(name, plan, flm, steps, warmup):
+    import torch
+
+    f = torch.empty_like(flm)
+    g = torch.empty_like(flm)
+    for _ in range(warmup):
+        plan.inverse(flm, out=f)
+        plan.forward(f, out=g)
+    torch.cuda.synchronize()
+    plan.set_profiling(True, only="apply_forward")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.inverse(flm, out=f)
+        plan.forward(f, out=g)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n, ms = plan.kernel_time("apply_forward")
+    plan.set_profiling(False)
+    return {"seconds": dt, "f": f, "g": g, "apply_forward_launches": n, "apply_forward_ms": ms}
+
+
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: the transforms run on a single device; --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
@@ -91,79 +149,77 @@ def main():
 
     L, B = args.L, args.batch
     torch.cuda.set_device(0)
-    plan = Plan(L, 0)
     flm_h = inputs.coeffs(L, B, seed=5, weighted=True)
     flm = torch.as_tensor(flm_h).cuda()
-    f = torch.empty_like(flm)
-    g = torch.empty_like(flm)
-    for _ in range(args.warmup):
-        plan.inverse(flm, out=f)
-        plan.forward(f, out=g)
-    torch.cuda.synchronize()
-    g_h = g.cpu().numpy()
-    rt_err = float(np.max(np.abs(g_h - flm_h)) / np.max(np.abs(flm_h)))
+    paths = [s.strip() for s in args.paths.split(",") if s.strip()]
+    res = {}
+    for name in paths:
+        plan = Plan(L, 0, precision="fp32" if name == "mixed" else "fp64")
+        r = run_path(name, plan, flm, args.steps, args.warmup)
+        r["device_bytes"] = plan.info()["device_bytes"]
+        r["plan"] = plan
+        res[name] = r
 
-    plan.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.inverse(flm, out=f)
-        plan.forward(f, out=g)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = dt / args.steps * 1e3
+    def rel(a, b):
+        return float((a - b).abs().max() / b.abs().max())
 
-    # per-kernel event timings of the timed region
-    kern = {}
-    for name in ("apply_inverse", "apply_forward", "ring_analysis", "ring_synthesis"):
-        n, ms = plan.kernel_time(name)
-        kern[name] = {"launches": n, "ms_total": ms}
-    plan.set_profiling(False)
-    # algorithmic work of one step's apply GEMMs: every signed order m streams
-    # an L x (L-|m|) FP64 block against 2B real columns -> 4 B L^3 flop per
-    # direction; each direction streams L^2 (L+1)/2 matrix entries once.
-    flop_dir = 4.0 * B * L ** 3
-    bytes_dir = 8.0 * L * L * (L + 1) / 2
-    for name in ("apply_inverse", "apply_forward"):
-        k = kern[name]
-        if k["ms_total"] > 0:
-            k["tflops"] = flop_dir * args.steps / (k["ms_total"] * 1e-3) / 1e12
-            k["gbs_matrix"] = bytes_dir * args.steps / (k["ms_total"] * 1e-3) / 1e9
-    dom = max(("apply_inverse", "apply_forward"), key=lambda n: kern[n]["ms_total"])
-    ach = kern[dom].get("tflops", 0.0)
-    roof = {"bound": "mfma", "kernel": dom, "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": ach / PEAK_FP64_TFLOPS, "traffic": None}
+    head = paths[0]
+    out_paths = {}
+    for name, r in res.items():
+        ms_step = r["seconds"] / args.steps * 1e3
+        ach = forward_apply_flops(L, B) * args.steps / (r["apply_forward_ms"] * 1e-3) / 1e12 \
+            if r["apply_forward_ms"] > 0 else 0.0
+        out_paths[name] = {
+            "sht_per_s": B * args.steps / r["seconds"],
+            "ms_per_step": ms_step,
+            "max_rel_err_roundtrip": rel(r["g"], flm),
+            "device_bytes": r["device_bytes"],
+            "apply_forward": {"launches": r["apply_forward_launches"], "ms_total": r["apply_forward_ms"],
+                              "tflops": ach},
+        }
+    if "fp64" in res and len(res) > 1:
+        for name in res:
+            if name != "fp64":
+                out_paths[name]["max_rel_err_inverse_vs_fp64"] = rel(res[name]["f"], res["fp64"]["f"])
+                # forward on the FP64 path's samples, against the FP64 forward
+                g = res[name]["plan"].forward(res["fp64"]["f"])
+                out_paths[name]["max_rel_err_forward_vs_fp64"] = rel(g, res["fp64"]["g"])
+        out_paths[head]["speedup_vs_fp64"] = out_paths[head]["sht_per_s"] / out_paths["fp64"]["sht_per_s"]
 
-    # sampled check of the inverse against the oracle on a few rings
+    # sampled check of the headline inverse against the oracle on a few rings
     from oracle import sht as osht
     from tests.gpu_util import oracle_plan
     rings = [0, 1, L // 2, L - 1]
     ref = osht.inverse_rings(oracle_plan(L), flm_h[:2], rings)
-    f_h = f.cpu().numpy()
+    f_h = res[head]["f"].cpu().numpy()
     inv_err = 0.0
     for k, v in ref.items():
         got = f_h[:2, k * k:k * k + 2 * k + 1]
         inv_err = max(inv_err, float(np.max(np.abs(got - v)) / np.max(np.abs(v))))
 
+    hp = out_paths[head]
+    peak = PEAK_TFLOPS[head]
+    roof = {"bound": "mfma", "kernel": "gemm_kernel<..., RoleApplyForward> (apply_forward)",
+            "achieved": hp["apply_forward"]["tflops"], "peak": peak, "unit": "TFLOP/s",
+            "frac": hp["apply_forward"]["tflops"] / peak, "traffic": None}
     out = {
         "metric": "fwd+inv SHT/s at L=1024, batch 16 (mixed vs FP64, max rel err); HBM GB/s",
-        "value": B * args.steps / dt,
+        "value": hp["sht_per_s"],
         "unit": "SHT/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": hp["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32 apply + f64" if head == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"spin-0 forward+inverse SHT, L={L}, batch {B}, flm N(0,1)(1+l)^-1 seed 5",
-                   "L": L, "batch": B, "spin": 0, "path": "fp64", "parallelism": "single-gpu"},
-        "max_rel_err_roundtrip": rt_err,
+        "config": {"workload": f"spin-0 inverse then forward SHT, L={L}, batch {B}, flm N(0,1)(1+l)^-1 seed 5",
+                   "L": L, "batch": B, "spin": 0, "path": head, "parallelism": "single-gpu"},
+        "paths": out_paths,
         "max_rel_err_inverse_vs_oracle_sampled_rings": inv_err,
         "roofline": roof,
-        "kernels": kern,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L)

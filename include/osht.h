@@ -60,6 +60,11 @@ extern "C" {
 #define OSHT_THETA_GREEDY       0x00u  /* condition-number-minimising greedy */
 #define OSHT_THETA_ALTERNATING  0x10u  /* Eq. sampling_latitude */
 #define OSHT_THETA_MASK         0xf0u
+/* autotune the forward sweep's block shape (levels per block, columns per
+ * delta-solve workgroup) by timing candidates on this device at plan time;
+ * the choice is cached in theta_cache_dir as "tune_fwd_<arch>_L<L>_s<s>_p<prec>.txt"
+ * when that directory is given */
+#define OSHT_TUNE               0x100u
 
 typedef struct osht_plan osht_plan_t;
 
@@ -143,17 +148,59 @@ int osht_forward_adjoint(const osht_plan_t* plan, const void* flm_bar, void* f_b
                          int64_t batch, hipStream_t stream);
 
 /*
+ * Batch scheduler.  Runs a list of transforms of possibly different plans
+ * (uneven L and spin) as one unit on `stream`: jobs of the same plan run in
+ * list order on one internal stream (they share the plan's workspace), jobs
+ * of different plans run concurrently on up to 8 internal streams forked
+ * from and joined back into `stream`.  Each job's buffers follow the
+ * conventions of the single-transform calls (device, complex128,
+ * [batch][L*L], no overlap of in and out).  All jobs of one plan must use
+ * the same batch, and every plan must live on the current device.
+ *   graph_inout == NULL: the jobs are issued directly.
+ *   *graph_inout == NULL: the jobs are captured into a HIP graph, which is
+ *     launched and returned in *graph_inout (owned by the caller; free it
+ *     with osht_graph_destroy).
+ *   *graph_inout != NULL: if the job list equals the captured one (same
+ *     plans, directions, pointers and batches) the graph is relaunched;
+ *     otherwise it is replaced by a new capture.
+ * Asynchronous; the caller must not destroy a plan while a graph that
+ * references it may still be launched.  Kernel timing is off inside graphs.
+ */
+#define OSHT_DIR_INVERSE          0
+#define OSHT_DIR_FORWARD          1
+#define OSHT_DIR_INVERSE_ADJOINT  2
+#define OSHT_DIR_FORWARD_ADJOINT  3
+
+typedef struct {
+  const osht_plan_t* plan;
+  int32_t direction;   /* OSHT_DIR_* */
+  int32_t reserved;    /* 0 */
+  const void* in;
+  void* out;
+  int64_t batch;
+} osht_job_t;
+
+typedef struct osht_graph osht_graph_t;
+
+int osht_batch_run(const osht_job_t* jobs, int njobs, hipStream_t stream, osht_graph_t** graph_inout);
+/* Frees a graph returned by osht_batch_run (NULL accepted). */
+int osht_graph_destroy(osht_graph_t* graph);
+
+/*
  * Kernel timing.  With profiling enabled on a plan, each launch of the
- * library's hot kernels made by that plan is bracketed by a pair of HIP
- * events recorded on the launch stream; osht_plan_kernel_time waits for the
+ * library's hot kernels made by that plan (or, when only_name is not NULL,
+ * each launch with that name only) is bracketed by a pair of HIP events
+ * recorded on the launch stream; osht_plan_kernel_time waits for the
  * pending events of one kernel name and returns the number of launches and
  * their summed duration in milliseconds since profiling was (re)enabled.
- * Names: "apply_inverse", "apply_forward", "apply_inverse_adjoint",
- * "apply_forward_adjoint" (order-wise GEMMs), "ring_analysis",
- * "ring_synthesis" (ring DFTs), "gather_forward", "gather_forward_adjoint".
+ * Names: "apply_inverse", "apply_forward", "apply_forward_correction",
+ * "apply_inverse_adjoint", "apply_forward_adjoint" (order-wise GEMMs),
+ * "ring_analysis", "ring_synthesis" (ring DFTs, one launch per FFT size
+ * class), "fold", "gather_forward", "delta_solve".
  * Unknown names return zero launches.  Enabling resets all counters.
+ * only_name is copied; NULL times every name.
  */
-int osht_plan_set_profiling(osht_plan_t* plan, int enable);
+int osht_plan_set_profiling(osht_plan_t* plan, int enable, const char* only_name);
 int osht_plan_kernel_time(osht_plan_t* plan, const char* name, int64_t* launches,
                           double* total_ms);
 

@@ -23,7 +23,7 @@ from . import _lib
 from ._lib import OshtError, lib  # noqa: F401
 
 __all__ = ["Plan", "InverseSHT", "ForwardSHT", "theta_greedy", "theta_alternating", "lib", "OshtError",
-           "THETA_CACHE_DIR"]
+           "THETA_CACHE_DIR", "batch_run", "BatchGraph"]
 
 THETA_CACHE_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "theta")
 
@@ -47,9 +47,11 @@ class Plan:
     """A transform plan for band-limit L and spin s on the current device."""
 
     def __init__(self, L, spin=0, placement="greedy", precision="fp64", theta_cache_dir=THETA_CACHE_DIR,
-                 device=None):
-        """precision: "fp64" (FP64 throughout) or "fp32" (order-wise applies on
-        FP32-stored matrices with FP32 matrix cores; everything else FP64)."""
+                 device=None, tune=False):
+        """precision: "fp64" (FP64 throughout) or "fp32" (FP32 matrix-core
+        applies of A_m and P_m^{-1}; alias rows, DFTs and buffers FP64).
+        tune: time the forward sweep's block shapes on this device and keep
+        the fastest (cached in theta_cache_dir)."""
         import torch
 
         if placement not in ("greedy", "alternating"):
@@ -57,7 +59,8 @@ class Plan:
         if precision not in ("fp64", "fp32"):
             raise ValueError("precision must be 'fp64' or 'fp32'")
         flags = (_lib.OSHT_PREC_FP64 if precision == "fp64" else _lib.OSHT_PREC_FP32) | (
-            _lib.OSHT_THETA_GREEDY if placement == "greedy" else _lib.OSHT_THETA_ALTERNATING)
+            _lib.OSHT_THETA_GREEDY if placement == "greedy" else _lib.OSHT_THETA_ALTERNATING) | (
+            _lib.OSHT_TUNE if tune else 0)
         self.L, self.spin, self.precision = int(L), int(spin), precision
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._h = ctypes.c_void_p()
@@ -76,9 +79,10 @@ class Plan:
         _lib.check(lib().osht_plan_theta(self._h, num))
         return [int(v) for v in num]
 
-    def set_profiling(self, enable=True):
-        """Event timing of the library's named kernel launches (resets counters)."""
-        _lib.check(lib().osht_plan_set_profiling(self._h, 1 if enable else 0))
+    def set_profiling(self, enable=True, only=None):
+        """Event timing of the library's named kernel launches (resets
+        counters); `only` restricts timing to one kernel name."""
+        _lib.check(lib().osht_plan_set_profiling(self._h, 1 if enable else 0, only.encode() if only else None))
 
     def kernel_time(self, name):
         """(launches, total milliseconds) of a named kernel since profiling was enabled."""
@@ -131,6 +135,51 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class BatchGraph:
+    """A HIP graph captured by batch_run (freed with the object)."""
+
+    def __init__(self):
+        self._h = ctypes.c_void_p()
+
+    def close(self):
+        if self._h.value:
+            lib().osht_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_run(jobs, graph=None):
+    """Runs jobs = [(plan, direction, in_tensor, out_tensor), ...] as one
+    unit on the current stream (direction: "inverse", "forward",
+    "inverse_adjoint", "forward_adjoint").  With graph (a BatchGraph) the
+    jobs are captured into a HIP graph on first use and the graph is
+    replayed while the job list is unchanged."""
+    import torch
+
+    arr = (_lib.OshtJob * len(jobs))()
+    keep = []
+    for i, (plan, direction, x, y) in enumerate(jobs):
+        for t in (x, y):
+            if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_contiguous():
+                raise TypeError("batch jobs take contiguous complex128 tensors")
+            if t.device != plan.device:
+                raise ValueError("tensor and plan on different devices")
+        n = plan.L * plan.L
+        if x.numel() % n or x.numel() != y.numel():
+            raise ValueError(f"job {i}: expected matching (B, {n}) tensors")
+        arr[i] = _lib.OshtJob(plan._h.value, _lib.OSHT_DIR[direction], 0, x.data_ptr(), y.data_ptr(), x.numel() // n)
+        keep.append((x, y))
+    stream = torch.cuda.current_stream().cuda_stream
+    gp = ctypes.byref(graph._h) if graph is not None else None
+    _lib.check(lib().osht_batch_run(arr, len(jobs), ctypes.c_void_p(stream), gp))
+    return graph
 
 
 def _autograd():

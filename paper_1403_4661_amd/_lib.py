@@ -23,6 +23,7 @@ OSHT_PREC_FP64 = 0x0
 OSHT_PREC_FP32 = 0x1
 OSHT_THETA_GREEDY = 0x00
 OSHT_THETA_ALTERNATING = 0x10
+OSHT_TUNE = 0x100
 
 EXPORTED = (
     "osht_theta_greedy",
@@ -39,6 +40,8 @@ EXPORTED = (
     "osht_last_error_message",
     "osht_plan_set_profiling",
     "osht_plan_kernel_time",
+    "osht_batch_run",
+    "osht_graph_destroy",
 )
 
 
@@ -54,6 +57,20 @@ class OshtInfo(ctypes.Structure):
         ("max_kappa", ctypes.c_double),
         ("max_inv_residual", ctypes.c_double),
     ]
+
+
+class OshtJob(ctypes.Structure):
+    _fields_ = [
+        ("plan", ctypes.c_void_p),
+        ("direction", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("inp", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("batch", ctypes.c_int64),
+    ]
+
+
+OSHT_DIR = {"inverse": 0, "forward": 1, "inverse_adjoint": 2, "forward_adjoint": 3}
 
 
 class OshtError(RuntimeError):
@@ -92,7 +109,9 @@ def lib():
         fn = getattr(L, name)
         fn.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
         fn.restype = ctypes.c_int
-    L.osht_plan_set_profiling.argtypes = [vp, ctypes.c_int]
+    L.osht_batch_run.argtypes = [ctypes.POINTER(OshtJob), ctypes.c_int, vp, ctypes.POINTER(vp)]
+    L.osht_graph_destroy.argtypes = [vp]
+    L.osht_plan_set_profiling.argtypes = [vp, ctypes.c_int, ctypes.c_char_p]
     L.osht_plan_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
     L.osht_strerror.argtypes = [ctypes.c_int]

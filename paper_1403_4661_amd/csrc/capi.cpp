@@ -17,10 +17,6 @@
 using osht::Error;
 using osht::Plan;
 
-struct osht_plan {
-  Plan p;
-};
-
 namespace {
 
 thread_local std::string g_last_error;
@@ -158,7 +154,7 @@ int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_di
   if (prec != OSHT_PREC_FP64 && prec != OSHT_PREC_FP32)
     return fail(OSHT_ENOTSUP, "precision must be OSHT_PREC_FP64 or OSHT_PREC_FP32");
   if (theta != OSHT_THETA_GREEDY && theta != OSHT_THETA_ALTERNATING) return fail(OSHT_EINVAL, "unknown placement flag");
-  if (flags & ~(OSHT_PREC_MASK | OSHT_THETA_MASK)) return fail(OSHT_EINVAL, "unknown flag bits");
+  if (flags & ~(OSHT_PREC_MASK | OSHT_THETA_MASK | OSHT_TUNE)) return fail(OSHT_EINVAL, "unknown flag bits");
   osht_plan_t* h = nullptr;
   try {
     h = new osht_plan_t;
@@ -167,6 +163,7 @@ int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_di
     p.spin = spin;
     p.flags = flags;
     p.fp32 = prec == OSHT_PREC_FP32;
+    if (theta_cache_dir) p.cache_dir = theta_cache_dir;
     OSHT_HIP(hipGetDevice(&p.device));
     p.numer.assign(L, 0);
     if (theta == OSHT_THETA_ALTERNATING) {
@@ -247,7 +244,7 @@ int osht_forward_adjoint(const osht_plan_t* plan, const void* flm_bar, void* f_b
                        [&](Plan& p, const double* a, double* b) { osht::run_forward_adjoint(p, a, b, batch, stream); });
 }
 
-int osht_plan_set_profiling(osht_plan_t* plan, int enable) {
+int osht_plan_set_profiling(osht_plan_t* plan, int enable, const char* only_name) {
   if (!plan) return fail(OSHT_EINVAL, "plan is NULL");
   Plan& p = plan->p;
   try {
@@ -255,6 +252,7 @@ int osht_plan_set_profiling(osht_plan_t* plan, int enable) {
     DeviceGuard g(p.device);
     p.prof.reset();
     p.prof.enabled = enable != 0;
+    p.prof.only = only_name ? only_name : "";
   } catch (const Error& e) {
     return fail(e.code, e.msg);
   }
@@ -278,6 +276,31 @@ int osht_plan_kernel_time(osht_plan_t* plan, const char* name, int64_t* launches
     }
   } catch (const Error& e) {
     return fail(e.code, e.msg);
+  }
+  return OSHT_OK;
+}
+
+int osht_batch_run(const osht_job_t* jobs, int njobs, hipStream_t stream, osht_graph_t** graph_inout) {
+  if (njobs < 0 || (njobs > 0 && !jobs)) return fail(OSHT_EINVAL, "bad job list");
+  for (int i = 0; i < njobs; ++i) {
+    const osht_job_t& j = jobs[i];
+    if (!j.plan || !j.in || !j.out) return fail(OSHT_EINVAL, "job " + std::to_string(i) + ": NULL plan or buffer");
+    if (j.direction < OSHT_DIR_INVERSE || j.direction > OSHT_DIR_FORWARD_ADJOINT || j.reserved != 0)
+      return fail(OSHT_EINVAL, "job " + std::to_string(i) + ": bad direction");
+    if (j.batch < 1 || j.batch > 65535) return fail(OSHT_EINVAL, "job " + std::to_string(i) + ": batch out of range");
+    const size_t bytes = sizeof(double) * 2 * (size_t)j.plan->p.L * j.plan->p.L * (size_t)j.batch;
+    if (overlaps(j.in, j.out, bytes)) return fail(OSHT_EINVAL, "job " + std::to_string(i) + ": in and out overlap");
+    for (int k = 0; k < i; ++k)
+      if (jobs[k].plan == j.plan && jobs[k].batch != j.batch)
+        return fail(OSHT_EINVAL, "jobs of one plan must share the batch size");
+  }
+  if (njobs == 0) return OSHT_OK;
+  try {
+    osht::batch_run(jobs, njobs, stream, graph_inout);
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(OSHT_ENOMEM, "host allocation failed");
   }
   return OSHT_OK;
 }

@@ -89,7 +89,8 @@ struct GemmDesc {
   const double* B;
   double* C;
   int64_t sAr, sAc, sBr, sBc, sCr, sCc;
-  int32_t M, N, K, pad;
+  int32_t M, N, K;
+  int32_t fp32;   // A is float (else double)
   double alpha, beta;
 };
 
@@ -112,6 +113,8 @@ struct Profiler {
     double ms = 0.0;
   };
   bool enabled = false;
+  std::string only;  // when not empty, the one name that is timed
+  bool wants(const char* name) const { return enabled && (only.empty() || only == name); }
   std::vector<std::pair<std::string, Stat>> stats;
   std::vector<hipEvent_t> pool;
   hipEvent_t get();
@@ -140,7 +143,7 @@ struct FwdBlocks {
   std::vector<int32_t> wide_ptr, wide_slot, wide_row;  // block -> (slot, row) pairs of rings k < kthr
   int max_unk = 0;
   int64_t max_w = 0;                           // max W entries in one block
-  int cpw = 8;                                 // delta-solve columns per workgroup
+  int cpw = 2;                                 // delta-solve columns per workgroup
   int lds_limit = 160 * 1024;
   void clear_host() {
     for (auto* v : {&q0, &q1, &slot_ptr, &slot_list, &unk_ptr, &lev_blk_ptr, &lev_ptr, &unk_slot, &unk_r, &unk_m,
@@ -161,14 +164,15 @@ struct Plan {
   int nslots = 0;
   int ncols_per_map = 0;  // 4 (spin 0: +/- x re/im) or 2
   std::vector<int32_t> numer;
+  std::string cache_dir;      // placement / tuning cache directory ("" = none)
   std::vector<Slot> slots;
   double max_kappa = 0.0, max_resid = 0.0;
   // device memory
   DevBuf d_cos, d_sin, d_cosh, d_sinh;
   DevBuf d_slots;
-  DevBuf d_A, d_Q;            // FP64 blocks (released after the FP32 copies are made for FP32 plans)
-  DevBuf d_A32, d_Q32;        // FP32 copies, same offsets (FP32 plans)
-  bool fp32 = false;          // order-wise applies on FP32 matrices
+  DevBuf d_A, d_Q;            // FP64 blocks (FP32 plans release d_A and keep d_Q for the alias rows)
+  DevBuf d_A32, d_Q32;        // FP32 copies, same element offsets (FP32 plans)
+  bool fp32 = false;          // FP32 plan (see OSHT_PREC_FP32)
   DevBuf d_rings, d_chirp, d_twiddle, d_chirp_tab;
   std::vector<int32_t> h_ring_logM;
   int max_logM = 0;
@@ -179,6 +183,7 @@ struct Plan {
   DevBuf d_btask;
   DevBuf d_gdesc, d_gtask;    // GEMM descriptors for the transforms
   int64_t ws_batch = 0;
+  int64_t ws_version = 0;     // bumped whenever workspace or descriptor tables change
   std::vector<GemmDesc> h_gdesc;
   std::vector<GemmTask> h_gtask;
   std::mutex mu;
@@ -193,7 +198,7 @@ struct ProfScope {
   hipStream_t st;
   hipEvent_t e0 = nullptr;
   ProfScope(Profiler& p, const char* n, hipStream_t s) : P(p), name(n), st(s) {
-    if (P.enabled) {
+    if (P.wants(n)) {
       e0 = P.get();
       OSHT_HIP(hipEventRecord(e0, st));
     }
@@ -214,11 +219,15 @@ void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t s
 void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st);
 void run_inverse_adjoint(Plan& p, const double* fbar, double* flmbar, int64_t B, hipStream_t st);
 void run_forward_adjoint(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st);
+// Sizes the workspace and descriptor tables for batch B (synchronous; must
+// precede any graph capture of the transforms).
+void prepare_transforms(Plan& p, int64_t B);
+// batch scheduler (batch.cpp); jobs validated by the caller
+void batch_run(const osht_job_t* jobs, int n, hipStream_t stream, osht_graph_t** graph_inout);
 
 // GEMM (gemm.hip): tasks and descriptors already on the device.
 enum class GemmRole { Plan, ApplyInverse, ApplyForward, Correction, Adjoint };
-void launch_gemm(GemmRole role, bool fp32_matrix, const GemmDesc* d_desc, const GemmTask* d_task, int ntask,
-                 hipStream_t st);
+void launch_gemm(GemmRole role, const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st);
 // Builds tasks for descriptors (64 x 64 tiles).
 void gemm_tasks(const std::vector<GemmDesc>& descs, std::vector<GemmTask>& tasks);
 
@@ -231,6 +240,12 @@ void launch_ring_analysis(const Plan& p, const double* f, double* H, int64_t B, 
 
 // blocked forward sweep (sweep.hip)
 void build_fwd_blocks(Plan& p, int b);
+// builds the blocks for b; true when the delta solve's LDS need fits
+bool fwd_blocks_fit(Plan& p, int b);
+// times the forward for candidate (b, delta-solve columns per group) and
+// keeps the fastest; results cached per (device, L, spin, precision) in
+// Plan::cache_dir when set
+void tune_forward_blocks(Plan& p);
 void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st);
 
 // placement (theta.cpp)
@@ -243,3 +258,8 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int round_up(int a, int b) { return (int)ceil_div(a, b) * b; }
 
 }  // namespace osht
+
+// Opaque handle of the C ABI.
+struct osht_plan {
+  osht::Plan p;
+};

@@ -1,25 +1,35 @@
 // Ring DFTs of the odd lengths n = 2k+1 (k = 0..L-1) by Bluestein's chirp-z
-// algorithm on power-of-two FFTs held in LDS.
+// algorithm on power-of-two FFTs held in registers.
 //
 // Analysis (ring k, one map):      H[q] = s * sum_j f_j e^{-2 pi i q j / n}
 // Synthesis:                       f_j  =     sum_q H[q] e^{+2 pi i q j / n}
 // With w_t = e^{-i pi t^2 / n} and q j = (q^2 + j^2 - (q-j)^2)/2,
 //     H[q] = s * w_q * sum_j (f_j w_j) conj(w_{q-j}),
-// a linear convolution evaluated by FFTs of size M >= 2n-1: a forward DIT
-// FFT (bit-reversed in, natural out), a pointwise product with the FFT of
-// the wrapped conjugate chirp b_t = conj(w_t), t in (-n, n) (computed once
-// per plan), and an inverse DIF FFT (natural in, bit-reversed out).
-// Synthesis is conj(analysis(conj(H))) without the 1/n.  Chirp phases are
-// reduced exactly as (t^2 mod 2n)/n and tabulated per ring at plan time.
+// a linear convolution evaluated with FFTs of size M >= max(16, 2n-1): a
+// forward FFT of the chirped input, a pointwise product with the FFT of the
+// wrapped conjugate chirp b_t = conj(w_t), t in (-n, n) (one table per ring,
+// built with the plan), and an inverse FFT.  Synthesis is
+// conj(analysis(conj(H))) without the 1/n.  Chirp phases are reduced exactly
+// as (t^2 mod 2n)/n.
 //
-// FFT passes are radix 4 (two radix-2 stages fused; one radix-2 stage when
-// log2 M is odd).  Twiddles e^{-2 pi i j/Mmax} are the product of two small
-// tables T1[j >> 6] T2[j & 63] kept in LDS.  Rings are launched by FFT size
-// class so that each launch reserves only the LDS its rings need.
+// FFT: Stockham autosort passes of radix 16 (one final pass of radix 2, 4 or
+// 8 when log2 M is not a multiple of 4).  Each FFT is owned by T = M/16
+// threads holding 16 points each in registers: thread t owns points
+// t + i T, i = 0..15, both at the start of the forward FFT and at the end of
+// every FFT, so the chirp products, the pointwise product between the two
+// FFTs and the output stores need no LDS.  The passes in between exchange
+// through LDS (padded by one point per 16 against bank conflicts).  Pass
+// (Ns, R) maps butterfly j, inputs x[j + r M/R], to outputs
+// y[(j / Ns) Ns R + j % Ns + r Ns] after twiddles w^r,
+// w = e^{-+2 pi i (j % Ns)/(Ns R)}, read from an e^{-2 pi i e/Mmax} table.
 //
-// Layouts: samples and coefficients of the C ABI are [b][L^2]; ring bins are
-// kept map-fastest, H[(k^2 + q) * B + b], which is what the order-wise GEMMs
-// read.  One workgroup handles one (ring, map).
+// Work: one launch per FFT-size class (rings sharing M).  A workgroup runs F
+// = blockDim/T FFTs, one per (ring, map) pair of the class; pairs are
+// map-fastest so a workgroup's maps share the ring, and workgroup ids are
+// remapped so that consecutive pairs stay on one XCD (one L2) -- the map
+// -fastest bin array H[(k^2 + q) B + b] is then written by nearby pairs.
+
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -34,256 +44,367 @@ __device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y *
 __device__ __forceinline__ cplx cconj(cplx a) { return {a.x, -a.y}; }
 __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.x - b.x, a.y - b.y}; }
-__device__ __forceinline__ cplx cmul_negi(cplx a) { return {a.y, -a.x}; }  // a * (-i)
 
-__device__ __forceinline__ unsigned bitrev(unsigned v, int bits) {
-  return bits == 0 ? 0u : (__brev(v) >> (32 - bits));
+constexpr int RPT = 16;  // points per thread
+
+// e^{-2 pi i j/16} (forward); the inverse uses the conjugate.
+__device__ __forceinline__ cplx w16(int j, bool inv) {
+  constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, h = 0.70710678118654752440;
+  const double cs[16] = {1.0, c1, h, s1, 0.0, -s1, -h, -c1, -1.0, -c1, -h, -s1, 0.0, s1, h, c1};
+  const double sn[16] = {0.0, -s1, -h, -c1, -1.0, -c1, -h, -s1, 0.0, s1, h, c1, 1.0, c1, h, s1};
+  return {cs[j], inv ? -sn[j] : sn[j]};
 }
 
-struct Tw {
-  const cplx* t1;  // e^{-2 pi i 64 a / Mmax}
-  const cplx* t2;  // e^{-2 pi i c / Mmax}, c < 64
-  int shift;       // log2(Mmax / M)
-  bool inverse;
-  __device__ __forceinline__ cplx operator()(int j) const {  // e^{-+2 pi i j / M}
-    const int J = j << shift;
-    cplx w = cmul(t1[J >> 6], t2[J & 63]);
-    if (inverse) w.y = -w.y;
-    return w;
+// v * e^{-+2 pi i j/16} with the exact cases spelled out.
+template <int J, bool INV>
+__device__ __forceinline__ cplx rot16(cplx v) {
+  if constexpr (J == 0) return v;
+  else if constexpr (J == 4) return INV ? cplx{-v.y, v.x} : cplx{v.y, -v.x};
+  else if constexpr (J == 8) return {-v.x, -v.y};
+  else if constexpr (J == 12) return INV ? cplx{v.y, -v.x} : cplx{-v.y, v.x};
+  else return cmul(v, w16(J, INV));
+}
+
+// In-register natural-order DFT of size R on x[0], x[S], ..., x[(R-1) S].
+template <int R, int S, bool INV>
+struct Dft {
+  template <int K>
+  static __device__ __forceinline__ void combine(cplx* x, const cplx* e, const cplx* o) {
+    if constexpr (K < R / 2) {
+      const cplx t = rot16<K * (16 / R), INV>(o[K]);
+      x[K * S] = cadd(e[K], t);
+      x[(K + R / 2) * S] = csub(e[K], t);
+      combine<K + 1>(x, e, o);
+    }
+  }
+  static __device__ __forceinline__ void run(cplx* x) {
+    if constexpr (R == 1) {
+      return;
+    } else if constexpr (R == 2) {
+      const cplx a = x[0], b = x[S];
+      x[0] = cadd(a, b);
+      x[S] = csub(a, b);
+    } else {
+      cplx e[R / 2], o[R / 2];
+#pragma unroll
+      for (int i = 0; i < R / 2; ++i) {
+        e[i] = x[2 * i * S];
+        o[i] = x[(2 * i + 1) * S];
+      }
+      Dft<R / 2, 1, INV>::run(e);
+      Dft<R / 2, 1, INV>::run(o);
+      combine<0>(x, e, o);
+    }
   }
 };
 
-// In-place DIT FFT of size M = 2^logM (bit-reversed input, natural output).
-__device__ void fft_dit(cplx* x, int logM, const Tw& tw) {
-  const int M = 1 << logM;
-  int s = 0;  // number of radix-2 stages done
-  if (logM & 1) {
-    for (int i = threadIdx.x; i < M / 2; i += blockDim.x) {
-      const cplx u = x[2 * i], v = x[2 * i + 1];
-      x[2 * i] = cadd(u, v);
-      x[2 * i + 1] = csub(u, v);
+struct FftCtx {
+  cplx* lds;        // this FFT's LDS region (M + M/16 points)
+  const cplx* tw;   // e^{-2 pi i e / Mmax}
+  int logM, logMmax, t, T;
+};
+
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+// One Stockham pass of radix R over the thread's 16 points, held as
+// butterflies c = 0..16/R-1 with element r of butterfly c in v[c + r (16/R)].
+template <int R, bool INV>
+__device__ __forceinline__ void pass_compute(cplx* v, const FftCtx& cx, int Ns) {
+  constexpr int NB = RPT / R;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const int j = cx.t + c * cx.T;
+    const int e = j & (Ns - 1);
+    if (Ns > 1 && e != 0) {
+      // w^r = tw[r * E], E = e * Mmax / (Ns R); w^r from w, w^2, w^4, w^8
+      const int E = e << (cx.logMmax - (31 - __clz(Ns * R)));
+      cplx p[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if ((1 << b) < R) {
+          p[b] = cx.tw[E << b];
+          if (INV) p[b].y = -p[b].y;
+        }
+      }
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cplx w;
+        bool have = false;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if (r & (1 << b)) {
+            w = have ? cmul(w, p[b]) : p[b];
+            have = true;
+          }
+        }
+        v[c + r * NB] = cmul(v[c + r * NB], w);
+      }
     }
-    __syncthreads();
-    s = 1;
-  }
-  for (; s < logM; s += 2) {
-    const int h = 1 << s;  // half-size of the first fused stage
-    for (int bf = threadIdx.x; bf < M / 4; bf += blockDim.x) {
-      const int pos = bf & (h - 1);
-      const int base = (bf >> s) << (s + 2);
-      cplx* p = x + base + pos;
-      const cplx w1 = tw(pos << (logM - s - 1));  // W_{2h}^{pos}
-      const cplx w2 = tw(pos << (logM - s - 2));  // W_{4h}^{pos}
-      const cplx a0 = p[0], a1 = cmul(w1, p[h]), a2 = p[2 * h], a3 = cmul(w1, p[3 * h]);
-      const cplx b0 = cadd(a0, a1), b1 = csub(a0, a1), b2 = cadd(a2, a3), b3 = csub(a2, a3);
-      const cplx t2 = cmul(w2, b2);
-      cplx t3 = cmul(w2, b3);
-      t3 = tw.inverse ? cplx{-t3.y, t3.x} : cmul_negi(t3);  // W_{4h}^{pos+h} = -+i W_{4h}^{pos}
-      p[0] = cadd(b0, t2);
-      p[2 * h] = csub(b0, t2);
-      p[h] = cadd(b1, t3);
-      p[3 * h] = csub(b1, t3);
-    }
-    __syncthreads();
+    Dft<R, NB, INV>::run(v + c);
   }
 }
 
-// In-place DIF FFT (natural input, bit-reversed output).
-__device__ void fft_dif(cplx* x, int logM, const Tw& tw) {
-  const int M = 1 << logM;
-  int s = logM;  // stages remaining, largest half first
-  for (; s >= 2; s -= 2) {
-    const int h = 1 << (s - 2);  // pairs (pos, pos+2h) then (pos, pos+h)
-    for (int bf = threadIdx.x; bf < M / 4; bf += blockDim.x) {
-      const int pos = bf & (h - 1);
-      const int base = (bf >> (s - 2)) << s;
-      cplx* p = x + base + pos;
-      const cplx w2 = tw(pos << (logM - s));      // W_{4h}^{pos}
-      const cplx w1 = tw(pos << (logM - s + 1));  // W_{2h}^{pos}
-      const cplx a0 = p[0], a1 = p[h], a2 = p[2 * h], a3 = p[3 * h];
-      const cplx b0 = cadd(a0, a2), b1 = cadd(a1, a3);
-      const cplx b2 = cmul(w2, csub(a0, a2));
-      cplx d = csub(a1, a3);
-      d = tw.inverse ? cplx{-d.y, d.x} : cmul_negi(d);
-      const cplx b3 = cmul(w2, d);
-      p[0] = cadd(b0, b1);
-      p[h] = cmul(w1, csub(b0, b1));
-      p[2 * h] = cadd(b2, b3);
-      p[3 * h] = cmul(w1, csub(b2, b3));
-    }
-    __syncthreads();
+template <int R>
+__device__ __forceinline__ void pass_store(const cplx* v, const FftCtx& cx, int Ns) {
+  constexpr int NB = RPT / R;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const int j = cx.t + c * cx.T;
+    const int base = (j / Ns) * Ns * R + (j & (Ns - 1));
+#pragma unroll
+    for (int r = 0; r < R; ++r) cx.lds[pad(base + r * Ns)] = v[c + r * NB];
   }
-  if (s == 1) {
-    for (int i = threadIdx.x; i < M / 2; i += blockDim.x) {
-      const cplx u = x[2 * i], v = x[2 * i + 1];
-      x[2 * i] = cadd(u, v);
-      x[2 * i + 1] = csub(u, v);
-    }
-    __syncthreads();
+}
+
+template <int R>
+__device__ __forceinline__ void pass_load(cplx* v, const FftCtx& cx) {
+  constexpr int NB = RPT / R;
+  const int M = 1 << cx.logM;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const int j = cx.t + c * cx.T;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[c + r * NB] = cx.lds[pad(j + r * (M / R))];
   }
+}
+
+// The radix of pass p (0-based) of the forward FFT: 16, ..., 16, small.
+constexpr int pass_radix(int logM, int p) { return p < (logM >> 2) ? 16 : (1 << (logM & 3)); }
+constexpr int num_passes(int logM) { return (logM + 3) >> 2; }
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
+
+// Pass P of an FFT of size 2^LOGM; Ns = product of the radices before it.
+template <bool INV, int LOGM, int P>
+struct FftPass {
+  static constexpr int NP = num_passes(LOGM);
+  static constexpr int R = INV ? pass_radix(LOGM, NP - 1 - P) : pass_radix(LOGM, P);
+  static __device__ __forceinline__ void run(cplx* v, const FftCtx& cx, int Ns) {
+    if constexpr (P > 0) {
+      __syncthreads();  // previous pass's stores visible
+      pass_load<R>(v, cx);
+    }
+    pass_compute<R, INV>(v, cx, Ns);
+    if constexpr (P < NP - 1) {
+      __syncthreads();  // all loads of this pass done before stores (in place)
+      pass_store<R>(v, cx, Ns);
+      FftPass<INV, LOGM, P + 1>::run(v, cx, Ns * R);
+    }
+  }
+};
+
+// Full FFT of size M = 2^LOGM (LOGM >= 4), points t + i T in v on entry and
+// exit (natural order).  Every thread of the workgroup must call it (it
+// contains barriers).  Forward: radix-16 passes then the small radix;
+// inverse (unscaled): the reverse order, so that the inverse starts from
+// the forward's output ownership.
+template <bool INV, int LOGM>
+__device__ __forceinline__ void fft(cplx* v, const FftCtx& cx) {
+  FftPass<INV, LOGM, 0>::run(v, cx, 1);
+}
+
+// Workgroup -> pair block, keeping consecutive pair blocks on one XCD
+// (workgroups are dispatched round-robin over 8 XCDs).
+__device__ __forceinline__ int xcd_remap(int bid, int G) {
+  const int q = G >> 3, r = G & 7, x = bid & 7, l = bid >> 3;
+  return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+struct PairCtx {
+  int k, b, n;
+  int64_t base, off;
+  bool active;
+};
+
+__device__ __forceinline__ PairCtx pair_of(const RingDesc* __restrict__ rings, int k0, int npairs, int B, int T) {
+  const int F = blockDim.x / T;
+  const int pair = xcd_remap(blockIdx.x, gridDim.x) * F + (int)(threadIdx.x / T);
+  PairCtx pc;
+  pc.active = pair < npairs;
+  const int pp = pc.active ? pair : 0;
+  pc.k = k0 + pp / B;
+  pc.b = pp % B;
+  const RingDesc r = rings[pc.k];
+  pc.n = r.n;
+  pc.off = r.off;
+  pc.base = (int64_t)pc.k * pc.k;
+  return pc;
 }
 
 extern __shared__ cplx lds_buf[];
 
-// LDS layout: [0, M) data, then T1 (Mmax/64 entries, at least 1), T2 (64).
-__device__ __forceinline__ Tw load_tw(const cplx* __restrict__ g_t1, const cplx* __restrict__ g_t2, int logMmax,
-                                      int logM, bool inverse) {
-  const int M = 1 << logM;
-  const int n1 = max(1, (1 << logMmax) >> 6);
-  cplx* t1 = lds_buf + M;
-  cplx* t2 = t1 + n1;
-  for (int i = threadIdx.x; i < n1; i += blockDim.x) t1[i] = g_t1[i];
-  for (int i = threadIdx.x; i < 64; i += blockDim.x) t2[i] = g_t2[i];
-  return Tw{t1, t2, logMmax - logM, inverse};
-}
-
 // Builds the FFT of the wrapped conjugate chirp for every ring of one size
-// class (rings k0 .. k0 + gridDim.x - 1).
-__global__ void chirp_kernel(const RingDesc* __restrict__ rings, int k0, const cplx* __restrict__ chirp_tab,
-                             cplx* __restrict__ table, const cplx* __restrict__ g_t1, const cplx* __restrict__ g_t2,
-                             int logMmax) {
-  const int k = k0 + blockIdx.x;
-  const RingDesc r = rings[k];
-  const int M = 1 << r.logM, n = r.n;
-  const Tw tw = load_tw(g_t1, g_t2, logMmax, r.logM, false);
-  cplx* x = lds_buf;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) x[i] = {0.0, 0.0};
-  __syncthreads();
-  const cplx* w = chirp_tab + (int64_t)k * k;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) {
-    const cplx b = cconj(w[t]);
-    x[bitrev(t, r.logM)] = b;
-    if (t > 0) x[bitrev(M - t, r.logM)] = b;
+// class: b_t = conj(w_t) for |t| < n (t < 0 stored at M + t), zero elsewhere.
+template <int LOGM>
+__global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void chirp_kernel(const RingDesc* __restrict__ rings, int k0,
+                                                                       int nrings, const cplx* __restrict__ chirp_tab,
+                                                                       cplx* __restrict__ table,
+                                                                       const cplx* __restrict__ tw, int logMmax) {
+  constexpr int logM = LOGM, M = 1 << LOGM, T = M / RPT;
+  const PairCtx pc = pair_of(rings, k0, nrings, 1, T);
+  const int t = threadIdx.x % T;
+  FftCtx cx{lds_buf + (threadIdx.x / T) * (M + M / 16), tw, logM, logMmax, t, T};
+  const cplx* w = chirp_tab + pc.base;
+  cplx v[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int p = t + i * T;
+    cplx b = {0.0, 0.0};
+    if (pc.active) {
+      if (p < pc.n) b = cconj(w[p]);
+      else if (p > M - pc.n) b = cconj(w[M - p]);
+    }
+    v[i] = b;
   }
-  __syncthreads();
-  fft_dit(x, r.logM, tw);
-  for (int i = threadIdx.x; i < M; i += blockDim.x) table[r.off + i] = x[i];
-}
-
-// Bluestein core: a_j (already times w_j) at bit-reversed positions of x,
-// zero elsewhere; leaves conv[q] at position bitrev(q), unscaled by 1/M.
-__device__ void bluestein_core(cplx* x, const RingDesc& r, const cplx* __restrict__ chirp_fft, const Tw& fwd,
-                               const Tw& inv) {
-  const int M = 1 << r.logM;
-  fft_dit(x, r.logM, fwd);
-  for (int i = threadIdx.x; i < M; i += blockDim.x) x[i] = cmul(x[i], chirp_fft[r.off + i]);
-  __syncthreads();
-  fft_dif(x, r.logM, inv);
-}
-
-// samples f[b][L^2] -> bins H[(k^2 + q) * B + b] (scale s = 1/n or 1).
-__global__ void ring_analysis_kernel(const RingDesc* __restrict__ rings, int k0, const cplx* __restrict__ chirp_fft,
-                                     const cplx* __restrict__ chirp_tab, const cplx* __restrict__ g_t1,
-                                     const cplx* __restrict__ g_t2, int logMmax, int L, const cplx* __restrict__ f,
-                                     cplx* __restrict__ H, int B, int normalise) {
-  const int k = k0 + blockIdx.x, b = blockIdx.y;
-  const RingDesc r = rings[k];
-  const int M = 1 << r.logM, n = r.n;
-  const int64_t base = (int64_t)k * k;
-  const Tw fwd = load_tw(g_t1, g_t2, logMmax, r.logM, false);
-  Tw inv = fwd;
-  inv.inverse = true;
-  cplx* x = lds_buf;
-  const cplx* w = chirp_tab + base;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) x[i] = {0.0, 0.0};
-  __syncthreads();
-  const cplx* fr = f + (int64_t)b * L * L + base;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) x[bitrev(j, r.logM)] = cmul(fr[j], w[j]);
-  __syncthreads();
-  bluestein_core(x, r, chirp_fft, fwd, inv);
-  const double sc = (normalise ? 1.0 / n : 1.0) / M;
-  for (int q = threadIdx.x; q < n; q += blockDim.x) {
-    const cplx c = cmul(x[bitrev(q, r.logM)], w[q]);
-    H[(base + q) * B + b] = {c.x * sc, c.y * sc};
+  fft<false, LOGM>(v, cx);
+  if (pc.active) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) table[pc.off + t + i * T] = v[i];
   }
 }
 
-// Synthesis of ring k, map b, with the bins taken either from the
-// map-fastest bin array H (optionally times 1/n), or folded from the
-// per-order GEMM output Y of the inverse transform:
-//   H[q] = sum_{m = q mod n, |m| < L} G'_m(theta_k),
+// Shared middle of analysis and synthesis: v holds the chirped input at
+// points t + i T; on return v holds the unscaled convolution at the same
+// points.
+template <int LOGM>
+__device__ __forceinline__ void bluestein(cplx* v, const FftCtx& cx, const cplx* __restrict__ cf, bool active) {
+  fft<false, LOGM>(v, cx);
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const cplx c = active ? cf[cx.t + i * cx.T] : cplx{0.0, 0.0};
+    v[i] = cmul(v[i], c);
+  }
+  fft<true, LOGM>(v, cx);
+}
+
+// samples f[b][L^2] -> bins H[(k^2 + q) * B + b] (scale 1/n or 1).
+template <int LOGM>
+__global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void ring_analysis_kernel(const RingDesc* __restrict__ rings, int k0,
+                                                            int npairs, const cplx* __restrict__ chirp_fft,
+                                                            const cplx* __restrict__ chirp_tab,
+                                                            const cplx* __restrict__ tw, int logMmax, int L,
+                                                            const cplx* __restrict__ f, cplx* __restrict__ H, int B,
+                                                            int normalise) {
+  constexpr int logM = LOGM, M = 1 << LOGM, T = M / RPT;
+  const PairCtx pc = pair_of(rings, k0, npairs, B, T);
+  const int t = threadIdx.x % T;
+  FftCtx cx{lds_buf + (threadIdx.x / T) * (M + M / 16), tw, logM, logMmax, t, T};
+  const cplx* w = chirp_tab + pc.base;
+  const cplx* fr = f + (int64_t)pc.b * L * L + pc.base;
+  cplx v[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int p = t + i * T;
+    v[i] = (pc.active && p < pc.n) ? cmul(fr[p], w[p]) : cplx{0.0, 0.0};
+  }
+  bluestein<LOGM>(v, cx, chirp_fft + pc.off, pc.active);
+  if (pc.active) {
+    const double sc = (normalise ? 1.0 / pc.n : 1.0) / M;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int q = t + i * T;
+      if (q < pc.n) {
+        const cplx c = cmul(v[i], w[q]);
+        H[(pc.base + q) * B + pc.b] = {c.x * sc, c.y * sc};
+      }
+    }
+  }
+}
+
+// Fold of the inverse transform's per-order values into ring bins:
+//   H[(k^2 + q) B + b] = sum_{m = q mod n_k, |m| < L} G'_m(theta_k),
 //   G'_m(theta_k) = Y[slot(m)][k][col(m, b)] (complex, two doubles).
 // Spin 0: slot(m) = |m|, col = (m < 0 ? 2B : 0) + 2b;  spin != 0:
-// slot(m) = m + L - 1, col = 2b.  Summation order is fixed (see the fold).
-__global__ void ring_synthesis_kernel(const RingDesc* __restrict__ rings, int k0, const cplx* __restrict__ chirp_fft,
-                                      const cplx* __restrict__ chirp_tab, const cplx* __restrict__ g_t1,
-                                      const cplx* __restrict__ g_t2, int logMmax, int L, const cplx* __restrict__ H,
-                                      int scale_inv_n, const double* __restrict__ Y, int spin0, int ncols,
-                                      cplx* __restrict__ f, int B) {
-  const int k = k0 + blockIdx.x, b = blockIdx.y;
-  const RingDesc r = rings[k];
-  const int M = 1 << r.logM, n = r.n;
+// slot(m) = m + L - 1, col = 2b.  One workgroup per ring; outputs are
+// map-fastest so that each (order, ring) row of Y is read as one contiguous
+// vector.  When the ring has fewer outputs than threads, each bin's order
+// list is split into C contiguous chunks whose partial sums are added in
+// chunk order (fixed summation order, deterministic).
+__global__ __launch_bounds__(256) void fold_kernel(const double* __restrict__ Y, cplx* __restrict__ H, int L, int B,
+                                                   int spin0, int ncols) {
+  __shared__ cplx part[256];
+  const int k = blockIdx.x, n = 2 * k + 1;
+  const int units = n * B;
+  const int C = max(1, (int)blockDim.x / units);
   const int64_t base = (int64_t)k * k;
-  const Tw fwd = load_tw(g_t1, g_t2, logMmax, r.logM, false);
-  Tw inv = fwd;
-  inv.inverse = true;
-  cplx* x = lds_buf;
-  const cplx* w = chirp_tab + base;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) x[i] = {0.0, 0.0};
-  __syncthreads();
-  if (Y == nullptr) {
-    for (int q = threadIdx.x; q < n; q += blockDim.x) {
-      cplx h = H[(base + q) * B + b];
-      if (scale_inv_n) { h.x /= n; h.y /= n; }
-      x[bitrev(q, r.logM)] = cmul(cconj(h), w[q]);
+  for (int u = threadIdx.x; u < units * C; u += blockDim.x) {
+    const int c = u / units, rem = u - c * units;
+    const int q = rem / B, b = rem - q * B;
+    const int mstart = q - ((q + L - 1) / n) * n;  // smallest m >= -(L-1) congruent to q
+    const int cnt = (L - 1 - mstart) / n + 1;
+    const int i0 = (int)((int64_t)cnt * c / C), i1 = (int)((int64_t)cnt * (c + 1) / C);
+    cplx h = {0.0, 0.0};
+    for (int i = i0; i < i1; ++i) {
+      const int m = mstart + i * n;
+      int slot, col;
+      if (spin0) { slot = m < 0 ? -m : m; col = (m < 0 ? 2 * B : 0) + 2 * b; }
+      else { slot = m + L - 1; col = 2 * b; }
+      const double2 y = *reinterpret_cast<const double2*>(Y + ((int64_t)slot * L + k) * ncols + col);
+      h.x += y.x;
+      h.y += y.y;
     }
-  } else {
-    // Fold: bin q collects the orders m = q (mod n), |m| < L.  When the ring
-    // has few bins, each bin's order list is split into C contiguous chunks
-    // summed by different threads, then the C partials are added in chunk
-    // order (fixed summation order, deterministic).
-    const int C = max(1, (int)blockDim.x / n);
-    cplx* part = lds_buf + M + max(1, (1 << logMmax) >> 6) + 64;  // C * n <= blockDim.x entries
-    for (int t = threadIdx.x; t < n * C; t += blockDim.x) {
-      const int q = t % n, c = t / n;
-      const int mstart = q - ((q + L - 1) / n) * n;  // smallest m >= -(L-1) congruent to q
-      const int cnt = (L - 1 - mstart) / n + 1;
-      const int i0 = (int)((int64_t)cnt * c / C), i1 = (int)((int64_t)cnt * (c + 1) / C);
-      cplx h = {0.0, 0.0};
-      for (int i = i0; i < i1; ++i) {
-        const int m = mstart + i * n;
-        int slot, col;
-        if (spin0) { slot = m < 0 ? -m : m; col = (m < 0 ? 2 * B : 0) + 2 * b; }
-        else { slot = m + L - 1; col = 2 * b; }
-        const double2 y = *reinterpret_cast<const double2*>(Y + ((int64_t)slot * L + k) * ncols + col);
-        h.x += y.x;
-        h.y += y.y;
-      }
-      if (C == 1) x[bitrev(q, r.logM)] = cmul(cconj(h), w[q]);
-      else part[c * n + q] = h;
-    }
-    if (C > 1) {
-      __syncthreads();
-      for (int q = threadIdx.x; q < n; q += blockDim.x) {
-        cplx h = part[q];
-        for (int c = 1; c < C; ++c) h = cadd(h, part[c * n + q]);
-        x[bitrev(q, r.logM)] = cmul(cconj(h), w[q]);
-      }
-    }
+    if (C == 1) H[(base + q) * B + b] = h;
+    else part[u] = h;
   }
-  __syncthreads();
-  bluestein_core(x, r, chirp_fft, fwd, inv);
-  const double sc = 1.0 / M;
-  cplx* fr = f + (int64_t)b * L * L + base;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const cplx c = cmul(x[bitrev(j, r.logM)], w[j]);
-    fr[j] = {c.x * sc, -c.y * sc};
+  if (C > 1) {
+    __syncthreads();
+    for (int u = threadIdx.x; u < units; u += blockDim.x) {
+      cplx h = part[u];
+      for (int c = 1; c < C; ++c) h = cadd(h, part[c * units + u]);
+      const int q = u / B, b = u - q * B;
+      H[(base + q) * B + b] = h;
+    }
   }
 }
 
-// Tables: T1[a] = e^{-2 pi i 64 a / Mmax}, T2[c] = e^{-2 pi i c / Mmax};
-// chirp_tab[k^2 + t] = e^{-i pi (t^2 mod 2n)/n}, n = 2k+1, t < n.
-__global__ void table_kernel(cplx* t1, cplx* t2, int Mmax, cplx* chirp_tab, int L) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int n1 = max(1, Mmax >> 6);
-  double s, c;
-  if (i < n1) {
-    sincospi(-2.0 * (double)(64 * i) / (double)Mmax, &s, &c);
-    t1[i] = {c, s};
+// Synthesis of (ring, map) pairs from the map-fastest bins H (optionally
+// times 1/n): f[b][k^2 + j] = sum_q H_k[q] e^{+2 pi i q j / n}.
+template <int LOGM>
+__global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void ring_synthesis_kernel(const RingDesc* __restrict__ rings, int k0,
+                                                             int npairs, const cplx* __restrict__ chirp_fft,
+                                                             const cplx* __restrict__ chirp_tab,
+                                                             const cplx* __restrict__ tw, int logMmax, int L,
+                                                             const cplx* __restrict__ H, int scale_inv_n,
+                                                             cplx* __restrict__ f, int B) {
+  constexpr int logM = LOGM, M = 1 << LOGM, T = M / RPT;
+  const PairCtx pc = pair_of(rings, k0, npairs, B, T);
+  const int t = threadIdx.x % T;
+  FftCtx cx{lds_buf + (threadIdx.x / T) * (M + M / 16), tw, logM, logMmax, t, T};
+  const cplx* w = chirp_tab + pc.base;
+  cplx v[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int q = t + i * T;
+    cplx h = {0.0, 0.0};
+    if (pc.active && q < pc.n) {
+      h = H[(pc.base + q) * B + pc.b];
+      if (scale_inv_n) { h.x /= pc.n; h.y /= pc.n; }
+      h = cmul(cconj(h), w[q]);
+    }
+    v[i] = h;
   }
-  if (i < 64) {
+  bluestein<LOGM>(v, cx, chirp_fft + pc.off, pc.active);
+  if (pc.active) {
+    const double sc = 1.0 / M;
+    cplx* fr = f + (int64_t)pc.b * L * L + pc.base;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int j = t + i * T;
+      if (j < pc.n) {
+        const cplx c = cmul(v[i], w[j]);
+        fr[j] = {c.x * sc, -c.y * sc};
+      }
+    }
+  }
+}
+
+// tw[e] = e^{-2 pi i e / Mmax}; chirp_tab[k^2 + t] = e^{-i pi (t^2 mod 2n)/n},
+// n = 2k+1, t < n.
+__global__ void table_kernel(cplx* tw, int Mmax, cplx* chirp_tab, int L) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double s, c;
+  if (i < Mmax) {
     sincospi(-2.0 * (double)i / (double)Mmax, &s, &c);
-    t2[i] = {c, s};
+    tw[i] = {c, s};
   }
   if (i < (int64_t)L * L) {
     int k = (int)sqrt((double)i);
@@ -296,22 +417,47 @@ __global__ void table_kernel(cplx* t1, cplx* t2, int Mmax, cplx* chirp_tab, int 
   }
 }
 
+// Launch shape of a size class: threads per workgroup and pairs per workgroup.
+struct Shape {
+  int nthr, F;
+  size_t lds;
+};
+
+Shape shape_for(int logM) {
+  const int T = (1 << logM) / RPT;
+  const int nthr = std::max(T, 256);
+  const int F = nthr / T;
+  const size_t per = (size_t)(1 << logM) + ((1 << logM) >> 4);
+  // a 16-point FFT stays in registers
+  const size_t lds = logM > 4 ? sizeof(cplx) * per * F : 0;
+  return Shape{nthr, F, lds};
+}
+
 void allow_lds(const void* fn, size_t bytes) {
   if (bytes > 65536) OSHT_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
-size_t lds_bytes(int logM, int logMmax) {
-  return sizeof(cplx) * (((size_t)1 << logM) + std::max(1, (1 << logMmax) >> 6) + 64 + 256);
-}
-
-int threads_for(int logM) {
-  const int bf = std::max(1, (1 << logM) / 4);
-  return bf >= 256 ? 256 : (bf >= 128 ? 128 : 64);
+// Calls fn(std::integral_constant<int, logM>) for logM in [4, 13].
+template <class Fn>
+void with_logM(int logM, Fn fn) {
+  switch (logM) {
+    case 4: fn(std::integral_constant<int, 4>{}); break;
+    case 5: fn(std::integral_constant<int, 5>{}); break;
+    case 6: fn(std::integral_constant<int, 6>{}); break;
+    case 7: fn(std::integral_constant<int, 7>{}); break;
+    case 8: fn(std::integral_constant<int, 8>{}); break;
+    case 9: fn(std::integral_constant<int, 9>{}); break;
+    case 10: fn(std::integral_constant<int, 10>{}); break;
+    case 11: fn(std::integral_constant<int, 11>{}); break;
+    case 12: fn(std::integral_constant<int, 12>{}); break;
+    case 13: fn(std::integral_constant<int, 13>{}); break;
+    default: throw Error{OSHT_ENOTSUP, "ring FFT size out of range"};
+  }
 }
 
 // Size classes: contiguous ring ranges [k_lo, k_hi) sharing logM.
-template <class F>
-void for_each_class(const Plan& p, F fn) {
+template <class Fn>
+void for_each_class(const Plan& p, Fn fn) {
   int k = 0;
   while (k < p.L) {
     const int logM = p.h_ring_logM[k];
@@ -328,68 +474,77 @@ void build_chirps(Plan& p) {
   const int L = p.L;
   std::vector<RingDesc> rings(L);
   int64_t off = 0;
-  int maxlog = 0;
+  int maxlog = 4;
   p.h_ring_logM.assign(L, 0);
   for (int k = 0; k < L; ++k) {
     const int n = 2 * k + 1;
-    int logM = 0;
+    int logM = 4;
     while ((1 << logM) < 2 * n - 1) ++logM;
     rings[k] = RingDesc{n, logM, off};
     p.h_ring_logM[k] = logM;
     off += (int64_t)1 << logM;
     maxlog = std::max(maxlog, logM);
   }
-  p.max_logM = std::max(maxlog, 1);
+  OSHT_CHECK(maxlog <= 13, OSHT_ENOTSUP, "ring FFTs above 8192 points are not supported");
+  p.max_logM = maxlog;
   upload(p.d_rings, rings);
   const int Mmax = 1 << p.max_logM;
-  const int n1 = std::max(1, Mmax >> 6);
-  p.d_twiddle.alloc(sizeof(cplx) * (n1 + 64));
+  p.d_twiddle.alloc(sizeof(cplx) * Mmax);
   p.d_chirp_tab.alloc(sizeof(cplx) * (size_t)L * L);
-  cplx* t1 = p.d_twiddle.as<cplx>();
-  cplx* t2 = t1 + n1;
-  const int64_t nthr = std::max<int64_t>((int64_t)L * L, std::max(n1, 64));
-  hipLaunchKernelGGL(table_kernel, dim3((unsigned)ceil_div(nthr, 256)), dim3(256), 0, 0, t1, t2, Mmax,
+  const int64_t nthr = std::max<int64_t>((int64_t)L * L, Mmax);
+  hipLaunchKernelGGL(table_kernel, dim3((unsigned)ceil_div(nthr, 256)), dim3(256), 0, 0, p.d_twiddle.as<cplx>(), Mmax,
                      p.d_chirp_tab.as<cplx>(), L);
   OSHT_HIP(hipGetLastError());
   p.d_chirp.alloc(sizeof(cplx) * off);
   for_each_class(p, [&](int k0, int k1, int logM) {
-    const size_t lds = lds_bytes(logM, p.max_logM);
-    allow_lds((const void*)chirp_kernel, lds);
-    hipLaunchKernelGGL(chirp_kernel, dim3(k1 - k0), dim3(threads_for(logM)), lds, 0, p.d_rings.as<RingDesc>(), k0,
-                       p.d_chirp_tab.as<cplx>(), p.d_chirp.as<cplx>(), t1, t2, p.max_logM);
-    OSHT_HIP(hipGetLastError());
+    with_logM(logM, [&](auto lg) {
+      constexpr int LG = decltype(lg)::value;
+      const Shape sh = shape_for(LG);
+      allow_lds((const void*)chirp_kernel<LG>, sh.lds);
+      const int np = k1 - k0;
+      hipLaunchKernelGGL(chirp_kernel<LG>, dim3((unsigned)ceil_div(np, sh.F)), dim3(sh.nthr), sh.lds, 0,
+                         p.d_rings.as<RingDesc>(), k0, np, p.d_chirp_tab.as<cplx>(), p.d_chirp.as<cplx>(),
+                         p.d_twiddle.as<cplx>(), p.max_logM);
+      OSHT_HIP(hipGetLastError());
+    });
   });
 }
 
 void launch_ring_analysis(const Plan& p, const double* f, double* H, int64_t B, bool normalise, hipStream_t st) {
-  const int Mmax = 1 << p.max_logM;
-  const cplx* t1 = p.d_twiddle.as<cplx>();
-  const cplx* t2 = t1 + std::max(1, Mmax >> 6);
   for_each_class(p, [&](int k0, int k1, int logM) {
-    const size_t lds = lds_bytes(logM, p.max_logM);
-    allow_lds((const void*)ring_analysis_kernel, lds);
-    hipLaunchKernelGGL(ring_analysis_kernel, dim3(k1 - k0, (unsigned)B), dim3(threads_for(logM)), lds, st,
-                       p.d_rings.as<RingDesc>(), k0, p.d_chirp.as<cplx>(), p.d_chirp_tab.as<cplx>(), t1, t2,
-                       p.max_logM, p.L, reinterpret_cast<const cplx*>(f), reinterpret_cast<cplx*>(H), (int)B,
-                       normalise ? 1 : 0);
-    OSHT_HIP(hipGetLastError());
+    with_logM(logM, [&](auto lg) {
+      constexpr int LG = decltype(lg)::value;
+      const Shape sh = shape_for(LG);
+      allow_lds((const void*)ring_analysis_kernel<LG>, sh.lds);
+      const int np = (k1 - k0) * (int)B;
+      hipLaunchKernelGGL(ring_analysis_kernel<LG>, dim3((unsigned)ceil_div(np, sh.F)), dim3(sh.nthr), sh.lds, st,
+                         p.d_rings.as<RingDesc>(), k0, np, p.d_chirp.as<cplx>(), p.d_chirp_tab.as<cplx>(),
+                         p.d_twiddle.as<cplx>(), p.max_logM, p.L, reinterpret_cast<const cplx*>(f),
+                         reinterpret_cast<cplx*>(H), (int)B, normalise ? 1 : 0);
+      OSHT_HIP(hipGetLastError());
+    });
   });
 }
 
-void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, const double* Y, double* f, int64_t B,
-                           hipStream_t st) {
-  const int Mmax = 1 << p.max_logM;
-  const cplx* t1 = p.d_twiddle.as<cplx>();
-  const cplx* t2 = t1 + std::max(1, Mmax >> 6);
+void launch_fold(const Plan& p, const double* Y, double* H, int64_t B, hipStream_t st) {
+  hipLaunchKernelGGL(fold_kernel, dim3(p.L), dim3(256), 0, st, Y, reinterpret_cast<cplx*>(H), p.L, (int)B,
+                     p.spin == 0 ? 1 : 0, p.ncols_per_map * (int)B);
+  OSHT_HIP(hipGetLastError());
+}
+
+void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, double* f, int64_t B, hipStream_t st) {
   for_each_class(p, [&](int k0, int k1, int logM) {
-    const size_t lds = lds_bytes(logM, p.max_logM);
-    allow_lds((const void*)ring_synthesis_kernel, lds);
-    const int nthr = Y ? 256 : threads_for(logM);  // folding small rings wants many threads
-    hipLaunchKernelGGL(ring_synthesis_kernel, dim3(k1 - k0, (unsigned)B), dim3(nthr), lds, st,
-                       p.d_rings.as<RingDesc>(), k0, p.d_chirp.as<cplx>(), p.d_chirp_tab.as<cplx>(), t1, t2,
-                       p.max_logM, p.L, reinterpret_cast<const cplx*>(H), scale_inv_n, Y, p.spin == 0 ? 1 : 0,
-                       p.ncols_per_map * (int)B, reinterpret_cast<cplx*>(f), (int)B);
-    OSHT_HIP(hipGetLastError());
+    with_logM(logM, [&](auto lg) {
+      constexpr int LG = decltype(lg)::value;
+      const Shape sh = shape_for(LG);
+      allow_lds((const void*)ring_synthesis_kernel<LG>, sh.lds);
+      const int np = (k1 - k0) * (int)B;
+      hipLaunchKernelGGL(ring_synthesis_kernel<LG>, dim3((unsigned)ceil_div(np, sh.F)), dim3(sh.nthr), sh.lds, st,
+                         p.d_rings.as<RingDesc>(), k0, np, p.d_chirp.as<cplx>(), p.d_chirp_tab.as<cplx>(),
+                         p.d_twiddle.as<cplx>(), p.max_logM, p.L, reinterpret_cast<const cplx*>(H), scale_inv_n,
+                         reinterpret_cast<cplx*>(f), (int)B);
+      OSHT_HIP(hipGetLastError());
+    });
   });
 }
 

@@ -19,9 +19,10 @@
 // the matrix core and then added into an FP64 running sum, so the FP32
 // accumulation error is that of a 16-term sum whatever K is.
 //
-// The Role parameter only names the kernel symbol (inverse apply, forward
-// apply, correction, adjoints, plan construction) so that per-kernel
-// profiles separate the launches.
+// The precision is chosen per descriptor (GemmDesc::fp32), so one launch
+// can mix FP32 and FP64 matrices.  The Role parameter only names the kernel
+// symbol (inverse apply, forward apply, correction, adjoints, plan
+// construction) so that per-kernel profiles separate the launches.
 
 #include "common.hpp"
 
@@ -98,17 +99,16 @@ __device__ __forceinline__ void store_tile(T (*As)[TM + P], T (*Bs)[TN + P], con
 // Software-pipelined: the global loads of k-tile t+1 are issued into
 // registers before the MFMAs of tile t run from LDS; LDS is double
 // buffered, so one barrier per k-tile suffices.
-template <bool ARF, bool BCF, class T, class Role>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs,
-                                                   const GemmTask* __restrict__ tasks) {
+template <bool ARF, bool BCF, class T>
+__device__ __forceinline__ void gemm_tile(const GemmDesc& d, const GemmTask& t, void* smem) {
   constexpr int P = Pad<T>::v;
   constexpr bool F64 = sizeof(T) == 8;
-  const GemmTask t = tasks[blockIdx.x];
-  const GemmDesc d = descs[t.desc];
+  typedef T RowA[TM + P];
+  typedef T RowB[TN + P];
+  RowA(*As)[TK] = reinterpret_cast<RowA(*)[TK]>(smem);                      // [2][TK][TM + P]
+  RowB(*Bs)[TK] = reinterpret_cast<RowB(*)[TK]>(static_cast<T*>(smem) + 2 * TK * (TM + P));
   const T* __restrict__ A = static_cast<const T*>(d.A);
   const int m0 = t.mt * TM, n0 = t.nt * TN;
-  __shared__ T As[2][TK][TM + P];
-  __shared__ T Bs[2][TK][TN + P];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   dbl4 acc[4];
 #pragma unroll
@@ -171,20 +171,151 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
   }
 }
 
-template <bool ARF, bool BCF, class T, class Role>
-void launch(const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st) {
-  hipLaunchKernelGGL((gemm_kernel<ARF, BCF, T, Role>), dim3(ntask), dim3(256), 0, st, d_desc, d_task);
+// Column-major A (the applies and the correction): each wave reads its own
+// 16-row A fragments straight from global memory into registers in the
+// MFMA operand layout (lane l: row l % 16, k = l / 16 of each 4-deep step;
+// 16 consecutive rows are 128 contiguous bytes), so A never passes through
+// LDS.  B (shared by the four waves) is staged through double-buffered LDS.
+// k-tiles are 32 deep; the next tile's A fragments and B elements are loaded
+// into registers while the current tile's MFMAs run.
+constexpr int TK2 = 32;
+constexpr int EB2 = TK2 * TN / 256;  // B elements per thread per tile (8)
+
+template <class T>
+__device__ __forceinline__ void load_a_frag(const GemmDesc& d, const T* __restrict__ A, int row, int k0, int kq,
+                                            T* a) {
+#pragma unroll
+  for (int s = 0; s < TK2 / 4; ++s) {
+    const int k = k0 + 4 * s + kq;
+    a[s] = (row < d.M && k < d.K) ? A[row + (int64_t)k * d.sAc] : T(0);
+  }
 }
 
 template <class T>
-void launch_role(GemmRole role, const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st) {
-  switch (role) {
-    case GemmRole::ApplyInverse: launch<true, true, T, RoleApplyInverse>(d_desc, d_task, ntask, st); break;
-    case GemmRole::ApplyForward: launch<true, true, T, RoleApplyForward>(d_desc, d_task, ntask, st); break;
-    case GemmRole::Correction: launch<true, true, T, RoleCorrection>(d_desc, d_task, ntask, st); break;
-    case GemmRole::Adjoint: launch<false, true, T, RoleAdjoint>(d_desc, d_task, ntask, st); break;
-    default: throw Error{OSHT_EINVAL, "bad GEMM role"};
+__device__ __forceinline__ void load_b2(const GemmDesc& d, int n0, int k0, T* rb) {
+#pragma unroll
+  for (int t = 0; t < EB2; ++t) {
+    const int j = threadIdx.x & 63, kk = (threadIdx.x >> 6) + 4 * t;
+    const int gk = k0 + kk, gj = n0 + j;
+    rb[t] = (gk < d.K && gj < d.N) ? T(d.B[(int64_t)gk * d.sBr + gj]) : T(0);
   }
+}
+
+template <class T, int P>
+__device__ __forceinline__ void store_b2(T (*Bs)[TN + P], const T* rb) {
+#pragma unroll
+  for (int t = 0; t < EB2; ++t) Bs[(threadIdx.x >> 6) + 4 * t][threadIdx.x & 63] = rb[t];
+}
+
+template <class T>
+__device__ __forceinline__ void gemm_tile_cm(const GemmDesc& d, const GemmTask& t, void* smem) {
+  constexpr int P = Pad<T>::v;
+  constexpr bool F64 = sizeof(T) == 8;
+  typedef T RowB[TN + P];
+  RowB(*Bs)[TK2] = reinterpret_cast<RowB(*)[TK2]>(smem);  // [2][TK2][TN + P]
+  const T* __restrict__ A = static_cast<const T*>(d.A);
+  const int m0 = t.mt * TM, n0 = t.nt * TN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = m0 + wave * 16 + (lane & 15), kq = lane >> 4;
+  dbl4 acc[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = dbl4{0.0, 0.0, 0.0, 0.0};
+  T a[TK2 / 4], an[TK2 / 4], rb[EB2];
+  const int nt = (d.K + TK2 - 1) / TK2;
+  if (nt > 0) {
+    load_a_frag<T>(d, A, row, 0, kq, a);
+    load_b2<T>(d, n0, 0, rb);
+    store_b2<T, P>(Bs[0], rb);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nt; ++kt) {
+    const int p = kt & 1;
+    const bool more = kt + 1 < nt;
+    if (more) {
+      load_a_frag<T>(d, A, row, (kt + 1) * TK2, kq, an);
+      load_b2<T>(d, n0, (kt + 1) * TK2, rb);
+    }
+    if constexpr (F64) {
+#pragma unroll
+      for (int s = 0; s < TK2 / 4; ++s) {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const double b = Bs[p][4 * s + kq][nb * 16 + (lane & 15)];
+          acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b, acc[nb], 0, 0, 0);
+        }
+      }
+    } else {
+      flt4 c[4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) c[nb] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < TK2 / 4; ++s) {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const float b = Bs[p][4 * s + kq][nb * 16 + (lane & 15)];
+          c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b, c[nb], 0, 0, 0);
+        }
+        if (s == TK2 / 8 - 1) {  // FP32 partial sums cover 16 k at most
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[nb][v] += (double)c[nb][v];
+            c[nb] = flt4{0.f, 0.f, 0.f, 0.f};
+          }
+        }
+      }
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[nb][v] += (double)c[nb][v];
+    }
+    if (more) {
+      store_b2<T, P>(Bs[p ^ 1], rb);
+#pragma unroll
+      for (int s = 0; s < TK2 / 4; ++s) a[s] = an[s];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = m0 + wave * 16 + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+      const int col = n0 + nb * 16 + (lane & 15);
+      if (r < d.M && col < d.N) {
+        double* cp = d.C + (int64_t)r * d.sCr + (int64_t)col * d.sCc;
+        double x = d.alpha * acc[nb][v];
+        if (d.beta != 0.0) x += d.beta * (*cp);
+        *cp = x;
+      }
+    }
+  }
+}
+
+// LDS of one tile pair: the FP64 layout is the larger one.
+constexpr int kSmemDoubles = 2 * 2 * TK * (TM + Pad<double>::v);
+static_assert(2 * TK * (TM + Pad<float>::v) * 2 * sizeof(float) <= kSmemDoubles * sizeof(double), "LDS size");
+static_assert(2 * TK2 * (TN + Pad<double>::v) <= kSmemDoubles, "LDS size");
+
+// Each task's descriptor selects the matrix precision (GemmDesc::fp32).
+template <bool ARF, bool BCF, class Role>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs,
+                                                   const GemmTask* __restrict__ tasks) {
+  __shared__ double smem[kSmemDoubles];
+  const GemmTask t = tasks[blockIdx.x];
+  const GemmDesc d = descs[t.desc];
+  if constexpr (ARF && BCF) {
+    if (d.fp32) gemm_tile_cm<float>(d, t, smem);
+    else gemm_tile_cm<double>(d, t, smem);
+  } else {
+    if (d.fp32) gemm_tile<ARF, BCF, float>(d, t, smem);
+    else gemm_tile<ARF, BCF, double>(d, t, smem);
+  }
+}
+
+template <bool ARF, bool BCF, class Role>
+void launch(const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st) {
+  hipLaunchKernelGGL((gemm_kernel<ARF, BCF, Role>), dim3(ntask), dim3(256), 0, st, d_desc, d_task);
 }
 
 }  // namespace
@@ -198,16 +329,14 @@ void gemm_tasks(const std::vector<GemmDesc>& descs, std::vector<GemmTask>& tasks
   }
 }
 
-void launch_gemm(GemmRole role, bool fp32_matrix, const GemmDesc* d_desc, const GemmTask* d_task, int ntask,
-                 hipStream_t st) {
+void launch_gemm(GemmRole role, const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st) {
   if (ntask <= 0) return;
-  if (role == GemmRole::Plan) {
-    OSHT_CHECK(!fp32_matrix, OSHT_EINVAL, "plan GEMMs run in FP64");
-    launch<true, false, double, RolePlan>(d_desc, d_task, ntask, st);
-  } else if (fp32_matrix) {
-    launch_role<float>(role, d_desc, d_task, ntask, st);
-  } else {
-    launch_role<double>(role, d_desc, d_task, ntask, st);
+  switch (role) {
+    case GemmRole::Plan: launch<true, false, RolePlan>(d_desc, d_task, ntask, st); break;
+    case GemmRole::ApplyInverse: launch<true, true, RoleApplyInverse>(d_desc, d_task, ntask, st); break;
+    case GemmRole::ApplyForward: launch<true, true, RoleApplyForward>(d_desc, d_task, ntask, st); break;
+    case GemmRole::Correction: launch<true, true, RoleCorrection>(d_desc, d_task, ntask, st); break;
+    case GemmRole::Adjoint: launch<false, true, RoleAdjoint>(d_desc, d_task, ntask, st); break;
   }
   OSHT_HIP(hipGetLastError());
 }

@@ -293,13 +293,13 @@ double newton_schulz(Plan& p, int s0, int s1, DevBuf& scratch, std::vector<doubl
   double best = INFINITY, last = INFINITY;
   int stall = 0;
   for (int it = 0; it < 120; ++it) {
-    launch_gemm(GemmRole::Plan, false, gPX.as<GemmDesc>(), kPX.as<GemmTask>(), (int)tPX.size(), 0);
+    launch_gemm(GemmRole::Plan, gPX.as<GemmDesc>(), kPX.as<GemmTask>(), (int)tPX.size(), 0);
     hipLaunchKernelGGL(ns_copy_kernel, dim3(64, ns), dim3(256), 0, 0, d_slots, s0, Q, scr, d_offXn.as<int64_t>(), 2.0, 0);
-    launch_gemm(GemmRole::Plan, false, gXT.as<GemmDesc>(), kXT.as<GemmTask>(), (int)tXT.size(), 0);
+    launch_gemm(GemmRole::Plan, gXT.as<GemmDesc>(), kXT.as<GemmTask>(), (int)tXT.size(), 0);
     hipLaunchKernelGGL(ns_copy_kernel, dim3(64, ns), dim3(256), 0, 0, d_slots, s0, Q, scr, d_offXn.as<int64_t>(), 1.0, 1);
     OSHT_HIP(hipGetLastError());
     if (it < 8) continue;
-    launch_gemm(GemmRole::Plan, false, gXP.as<GemmDesc>(), kXP.as<GemmTask>(), (int)tXP.size(), 0);
+    launch_gemm(GemmRole::Plan, gXP.as<GemmDesc>(), kXP.as<GemmTask>(), (int)tXP.size(), 0);
     hipLaunchKernelGGL(ns_resid_kernel, dim3(ns), dim3(256), 0, 0, d_slots, s0, scr, d_offE.as<int64_t>(), d_out.as<double>());
     OSHT_HIP(hipGetLastError());
     OSHT_HIP(hipMemcpy(res.data(), d_out.p, sizeof(double) * ns, hipMemcpyDeviceToHost));
@@ -429,35 +429,32 @@ void build_plan(Plan& p) {
     DevBuf gd, gt;
     upload(gd, dC);
     upload(gt, tC);
-    launch_gemm(GemmRole::Plan, false, gd.as<GemmDesc>(), gt.as<GemmTask>(), (int)tC.size(), 0);
+    launch_gemm(GemmRole::Plan, gd.as<GemmDesc>(), gt.as<GemmTask>(), (int)tC.size(), 0);
     OSHT_HIP(hipDeviceSynchronize());
   }
   build_chirps(p);
   // Block size of the forward sweep: the largest b <= 32 (or OSHT_FWD_BLOCK)
-  // whose alias system fits the delta solve's LDS with 8 columns per group.
+  // whose alias system fits the delta solve's LDS.
   int b = 32;
-  if (const char* env = std::getenv("OSHT_FWD_BLOCK")) b = std::max(1, std::atoi(env));
-  for (;;) {
-    build_fwd_blocks(p, b);
-    const size_t need = sizeof(double) * ((size_t)p.fb.max_unk * p.fb.cpw + p.fb.max_w) +
-                        sizeof(int32_t) * (p.fb.max_w + p.fb.max_unk + 1);
-    if (need <= (size_t)p.fb.lds_limit || b == 1) break;
-    b = std::max(1, b * 3 / 4);
-  }
+  const char* env = std::getenv("OSHT_FWD_BLOCK");
+  if (env) b = std::max(1, std::atoi(env));
+  while (!fwd_blocks_fit(p, b) && b > 1) b = std::max(1, b * 3 / 4);
   if (p.fp32) {
-    // FP32 copies at the same element offsets; the FP64 blocks are released
-    auto narrow = [](DevBuf& src, DevBuf& dst) {
+    // FP32 copies at the same element offsets.  A_m is released; Q_m stays
+    // in FP64 for its alias rows (A_m^top P_m^{-1}) and the forward adjoint
+    auto narrow = [](DevBuf& src, DevBuf& dst, bool release) {
       const int64_t n = (int64_t)(src.bytes / sizeof(double));
       dst.alloc(sizeof(float) * std::max<int64_t>(n, 1));
       hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(n, 256), 1), 8192)),
                          dim3(256), 0, 0, src.as<double>(), dst.as<float>(), n);
       OSHT_HIP(hipGetLastError());
       OSHT_HIP(hipDeviceSynchronize());
-      src.release();
+      if (release) src.release();
     };
-    narrow(p.d_A, p.d_A32);
-    narrow(p.d_Q, p.d_Q32);
+    narrow(p.d_A, p.d_A32, true);
+    narrow(p.d_Q, p.d_Q32, false);
   }
+  if ((p.flags & OSHT_TUNE) && !env) tune_forward_blocks(p);
   OSHT_HIP(hipDeviceSynchronize());
 }
 

@@ -19,7 +19,11 @@
 // Afterwards Y_m holds f_m and the exact aliases G'_m on the rings k < |m|,
 // which later blocks read in step 1.  All sums run in a fixed order.
 
+#include <unistd.h>
+
 #include <algorithm>
+#include <cstdio>
+#include <string>
 #include <cstdlib>
 
 #include "xform.hpp"
@@ -158,14 +162,27 @@ __global__ __launch_bounds__(512) void delta_solve_kernel(Geo g, int u0, int nu,
     dl[e] = acc;
   }
   __syncthreads();
-  // level-ordered substitution, LDS only
+  // level-ordered substitution, LDS only; each (unknown, column) item is
+  // reduced by a group of G lanes (strided partial sums, then a fixed
+  // butterfly over the group), so the per-level critical path is
+  // ~len(W row)/G steps
+  constexpr int G = 8;
+  const int grp = threadIdx.x / G, lg = threadIdx.x % G, ngrp = blockDim.x / G;
   for (int lv = 0; lv < nlev; ++lv) {
     const int a = lev_ptr[lv] - u0, b = lev_ptr[lv + 1] - u0;
-    for (int e = threadIdx.x; e < (b - a) * cpw; e += blockDim.x) {
-      const int ul = a + e / cpw, jj = e % cpw;
-      double acc = dl[ul * cpw + jj];
-      for (int w = wp[ul]; w < wp[ul + 1]; ++w) acc -= wv[w] * dl[wc[w] * cpw + jj];
-      dl[ul * cpw + jj] = acc;
+    const int items = (b - a) * cpw;
+    for (int e0 = 0; e0 < items; e0 += ngrp) {
+      const int e = e0 + grp;
+      double part = 0.0;
+      int ul = 0, jj = 0;
+      if (e < items) {
+        ul = a + e / cpw;
+        jj = e % cpw;
+        for (int w = wp[ul] + lg; w < wp[ul + 1]; w += G) part += wv[w] * dl[wc[w] * cpw + jj];
+      }
+#pragma unroll
+      for (int off = 1; off < G; off <<= 1) part += __shfl_xor(part, off, G);
+      if (e < items && lg == 0) dl[ul * cpw + jj] -= part;
     }
     __syncthreads();
   }
@@ -377,6 +394,100 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
     }
   }
   launch_fwd_scatter(p, p.w_Y.as<double>(), flm, B, st);
+}
+
+bool fwd_blocks_fit(Plan& p, int b) {
+  build_fwd_blocks(p, b);
+  const size_t need = sizeof(double) * ((size_t)p.fb.max_unk * p.fb.cpw + p.fb.max_w) +
+                      sizeof(int32_t) * (p.fb.max_w + p.fb.max_unk + 1);
+  return need <= (size_t)p.fb.lds_limit || b == 1;
+}
+
+namespace {
+
+__global__ void tune_fill_kernel(double* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = (double)((i * 2654435761ll) & 1023) / 512.0 - 1.0;
+}
+
+std::string tune_path(const Plan& p) {
+  if (p.cache_dir.empty()) return "";
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p.device) != hipSuccess) return "";
+  std::string arch = prop.gcnArchName;
+  for (char& c : arch)
+    if (c == ':' || c == '/' || c == ' ') c = '_';
+  return p.cache_dir + "/tune_fwd_" + arch + "_L" + std::to_string(p.L) + "_s" + std::to_string(p.spin) + "_p" +
+         std::to_string(p.fp32 ? 1 : 0) + ".txt";
+}
+
+}  // namespace
+
+void tune_forward_blocks(Plan& p) {
+  const std::string path = tune_path(p);
+  int best_b = -1, best_c = -1;
+  if (!path.empty()) {
+    if (FILE* fp = std::fopen(path.c_str(), "r")) {
+      if (std::fscanf(fp, "%d %d", &best_b, &best_c) != 2) best_b = best_c = -1;
+      std::fclose(fp);
+    }
+  }
+  if (best_b < 1 || best_c < 1) {
+    const int64_t Bt = p.spin == 0 ? 16 : 8;
+    const int64_t n = 2 * (int64_t)p.L * p.L * Bt;
+    DevBuf in, out;
+    in.alloc(sizeof(double) * n);
+    out.alloc(sizeof(double) * n);
+    hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, 0, in.as<double>(), n);
+    OSHT_HIP(hipGetLastError());
+    hipEvent_t e0, e1;
+    OSHT_HIP(hipEventCreate(&e0));
+    OSHT_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    const bool prof = p.prof.enabled;
+    p.prof.enabled = false;
+    for (int cpw : {1, 2, 4}) {
+      for (int b : {8, 12, 16, 24, 32, 48, 64}) {
+        if (b > p.L) continue;
+        p.fb.cpw = cpw;
+        if (!fwd_blocks_fit(p, b) && b > 1) continue;
+        p.ws_batch = 0;
+        run_forward(p, in.as<double>(), out.as<double>(), Bt, 0);
+        OSHT_HIP(hipEventRecord(e0, 0));
+        for (int r = 0; r < 3; ++r) run_forward(p, in.as<double>(), out.as<double>(), Bt, 0);
+        OSHT_HIP(hipEventRecord(e1, 0));
+        OSHT_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        OSHT_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) { best_ms = ms; best_b = b; best_c = cpw; }
+      }
+    }
+    p.prof.enabled = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    OSHT_HIP(hipDeviceSynchronize());
+    if (!path.empty() && best_b > 0) {
+      const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+      if (FILE* fp = std::fopen(tmp.c_str(), "w")) {
+        std::fprintf(fp, "%d %d\n# forward block levels, delta-solve columns per workgroup (%.3f ms for 3 forwards)\n",
+                     best_b, best_c, best_ms);
+        if (std::fclose(fp) == 0) std::rename(tmp.c_str(), path.c_str());
+        else std::remove(tmp.c_str());
+      }
+    }
+  }
+  if (best_b < 1) return;
+  p.fb.cpw = best_c;
+  if (!fwd_blocks_fit(p, best_b)) {
+    p.fb.cpw = 2;
+    int b = 32;
+    while (!fwd_blocks_fit(p, b) && b > 1) b = std::max(1, b * 3 / 4);
+  }
+  p.ws_batch = 0;
+  p.w_X.release();
+  p.w_Y.release();
+  p.w_H.release();
+  p.w_D.release();
 }
 
 }  // namespace osht

@@ -27,8 +27,8 @@
 
 namespace osht {
 
-void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, const double* Y, double* f, int64_t B,
-                           hipStream_t st);
+void launch_fold(const Plan& p, const double* Y, double* H, int64_t B, hipStream_t st);
+void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, double* f, int64_t B, hipStream_t st);
 
 namespace {
 
@@ -173,8 +173,10 @@ __global__ __launch_bounds__(256) void fadj_scatter_kernel(Geo g, const Slot* __
 }  // namespace
 
 // ---------------------------------------------------------------- host side
-const char* const kApplyName[kNumDir] = {"apply_inverse", "apply_forward", "apply_inverse_adjoint",
-                                         "apply_forward_adjoint", "apply_forward_correction"};
+const char* const kApplyName[kNumDir] = {"apply_inverse",           "apply_forward",
+                                         "apply_inverse_adjoint",   "apply_forward_adjoint",
+                                         "apply_forward_correction", "apply_forward",
+                                         "apply_forward_correction"};
 
 // Workspace and GEMM descriptors for batch B (rebuilt when B or the buffers
 // change).  Descriptor d = dir * nslots + slot; tasks of all directions are
@@ -191,14 +193,23 @@ void ensure_workspace(Plan& p, int64_t B) {
   p.w_H.reserve(hb);
   p.w_D.reserve(db);
   if (!grow && p.ws_batch == B && !p.h_gdesc.empty()) return;
+  // descriptor tables are rewritten below: earlier work on any stream may
+  // still read them
+  OSHT_HIP(hipDeviceSynchronize());
+  ++p.ws_version;
   p.h_gdesc.clear();
   double* X = p.w_X.as<double>();
   double* Y = p.w_Y.as<double>();
   double* D = p.w_D.as<double>();
-  // matrix element offsets are the same in the FP64 and FP32 copies
-  const char* A = static_cast<const char*>(p.fp32 ? p.d_A32.p : p.d_A.p);
-  const char* Q = static_cast<const char*>(p.fp32 ? p.d_Q32.p : p.d_Q.p);
-  const size_t es = p.fp32 ? sizeof(float) : sizeof(double);
+  // Matrix element offsets are the same in the FP64 and FP32 copies.  FP32
+  // plans apply A_m (inverse and its adjoint) and the coefficient rows of
+  // Q_m (P_m^{-1}) in FP32; the alias rows of Q_m (A_m^top P_m^{-1}), which
+  // feed the descending-order chain, and the forward adjoint stay FP64.
+  const double* A64 = p.d_A.as<double>();
+  const double* Q64 = p.d_Q.as<double>();
+  const float* A32 = p.d_A32.as<float>();
+  const float* Q32 = p.d_Q32.as<float>();
+  const bool f32 = p.fp32;
   const int bD = std::max(p.fb.b, 1);
   std::vector<int32_t> wcorr(p.nslots, 0);  // correction width per slot
   for (size_t blk = 0; blk + 1 < p.fb.slot_ptr.size(); ++blk)
@@ -216,14 +227,30 @@ void ensure_workspace(Plan& p, int64_t B) {
       d.B = Xs; d.sBr = ncols; d.sBc = 1;
       d.C = Ys; d.sCr = ncols; d.sCc = 1;
       d.N = (int)ncols; d.alpha = 1.0; d.beta = 0.0;
-      if (dir == kInv) { d.A = A + es * sl.offA; d.sAr = 1; d.sAc = sl.ldA; d.M = p.L; d.K = sl.K; }
-      if (dir == kFwd) { d.A = Q + es * sl.offQ; d.sAr = 1; d.sAc = sl.ldQ; d.M = sl.K + am; d.K = sl.R; }
-      if (dir == kIadj) { d.A = A + es * sl.offA; d.sAr = sl.ldA; d.sAc = 1; d.M = sl.K; d.K = p.L; }
-      if (dir == kFadj) { d.A = Q + es * sl.offQ; d.sAr = sl.ldQ; d.sAc = 1; d.M = sl.R; d.K = sl.K + am; }
-      if (dir == kCorr) {  // Y -= Q[:, 0:w] D
-        d.A = Q + es * sl.offQ; d.sAr = 1; d.sAc = sl.ldQ; d.M = sl.K + am; d.K = std::min(wcorr[i], sl.R);
-        d.B = D + (int64_t)i * bD * ncols;
-        d.alpha = -1.0; d.beta = 1.0;
+      auto setA = [&](bool use32, bool isA, int64_t off) {
+        d.fp32 = use32 ? 1 : 0;
+        if (use32) d.A = (isA ? A32 : Q32) + off;
+        else d.A = (isA ? A64 : Q64) + off;
+      };
+      if (dir == kInv) { setA(f32, true, sl.offA); d.sAr = 1; d.sAc = sl.ldA; d.M = p.L; d.K = sl.K; }
+      if (dir == kIadj) { setA(f32, true, sl.offA); d.sAr = sl.ldA; d.sAc = 1; d.M = sl.K; d.K = p.L; }
+      if (dir == kFadj) { setA(false, false, sl.offQ); d.sAr = sl.ldQ; d.sAc = 1; d.M = sl.R; d.K = sl.K + am; }
+      if (dir == kFwd || dir == kCorr || dir == kFwdAlias || dir == kCorrAlias) {
+        // rows [0, K) (coefficients) in the main descriptor, rows [K, K+|m|)
+        // (aliases) in the alias one when the plan is FP32
+        const bool alias = dir == kFwdAlias || dir == kCorrAlias;
+        const int r0 = alias ? sl.K : 0;
+        const int r1 = f32 ? (alias ? sl.K + am : sl.K) : (alias ? 0 : sl.K + am);
+        setA(f32 && !alias, false, sl.offQ + r0);
+        d.sAr = 1; d.sAc = sl.ldQ;
+        d.M = std::max(0, r1 - r0);
+        d.C = Ys + (int64_t)r0 * ncols;
+        d.K = sl.R;
+        if (dir == kCorr || dir == kCorrAlias) {  // Y -= Q[:, 0:w] D
+          d.K = std::min(wcorr[i], sl.R);
+          d.B = D + (int64_t)i * bD * ncols;
+          d.alpha = -1.0; d.beta = 1.0;
+        }
       }
       p.h_gdesc.push_back(d);
     }
@@ -244,15 +271,19 @@ void ensure_workspace(Plan& p, int64_t B) {
   for (int blk = 0; blk < nblk; ++blk) {
     const bool has_unk = p.fb.unk_ptr[blk + 1] > p.fb.unk_ptr[blk];
     p.h_btask_ptr.push_back((int32_t)bt.size());
-    for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) emit(kFwd * p.nslots + p.fb.slot_list[i]);
+    for (int dir : {kFwd, kFwdAlias})
+      for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) emit(dir * p.nslots + p.fb.slot_list[i]);
     p.h_btask_ptr.push_back((int32_t)bt.size());
     if (has_unk)
-      for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) emit(kCorr * p.nslots + p.fb.slot_list[i]);
+      for (int dir : {kCorr, kCorrAlias})
+        for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) emit(dir * p.nslots + p.fb.slot_list[i]);
   }
   p.h_btask_ptr.push_back((int32_t)bt.size());
   upload(p.d_btask, bt);
   p.ws_batch = B;
 }
+
+void prepare_transforms(Plan& p, int64_t B) { ensure_workspace(p, B); }
 
 void launch_fwd_scatter(const Plan& p, const double* Y, double* flm, int64_t B, hipStream_t st) {
   const Geo g = geo(p, B);
@@ -272,7 +303,7 @@ void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, GemmRole rol
                        hipStream_t st) {
   if (count <= 0) return;
   ProfScope ps(p.prof, prof_name, st);
-  launch_gemm(role, p.fp32, p.d_gdesc.as<GemmDesc>(), d_tasks, count, st);
+  launch_gemm(role, p.d_gdesc.as<GemmDesc>(), d_tasks, count, st);
 }
 
 namespace {
@@ -299,10 +330,10 @@ void gemm_slots(Plan& p, int dir, int s0, int s1, hipStream_t st) {
   int first, count;
   task_range(p, dir, s0, s1, first, count);
   // inverse / forward read A or Q column-major; the adjoints read them transposed
-  const GemmRole role = dir == kInv    ? GemmRole::ApplyInverse
-                        : dir == kFwd  ? GemmRole::ApplyForward
-                        : dir == kCorr ? GemmRole::Correction
-                                       : GemmRole::Adjoint;
+  const GemmRole role = dir == kInv                        ? GemmRole::ApplyInverse
+                        : (dir == kFwd || dir == kFwdAlias)  ? GemmRole::ApplyForward
+                        : (dir == kCorr || dir == kCorrAlias) ? GemmRole::Correction
+                                                              : GemmRole::Adjoint;
   gemm_tasks_launch(p, p.d_gtask.as<GemmTask>() + first, count, role, kApplyName[dir], st);
 }
 
@@ -322,8 +353,12 @@ void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t s
   (void)g;
   launch_coef_to_slots(p, flm, p.w_X.as<double>(), B, st);
   gemm_slots(p, kInv, 0, p.nslots, st);
+  {
+    ProfScope ps(p.prof, "fold", st);
+    launch_fold(p, p.w_Y.as<double>(), p.w_H.as<double>(), B, st);
+  }
   ProfScope ps(p.prof, "ring_synthesis", st);
-  launch_ring_synthesis(p, nullptr, 0, p.w_Y.as<double>(), f, B, st);
+  launch_ring_synthesis(p, p.w_H.as<double>(), 0, f, B, st);
 }
 
 void run_forward_levels(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {
@@ -344,12 +379,14 @@ void run_forward_levels(Plan& p, const double* f, double* flm, int64_t B, hipStr
                          p.w_H.as<double>(), p.w_Y.as<double>(), p.w_X.as<double>());
       OSHT_HIP(hipGetLastError());
       gemm_slots(p, kFwd, s0, s1, st);
+      gemm_slots(p, kFwdAlias, s0, s1, st);
     } else {
       for (int sl : {s0, s1 - 1}) {
         hipLaunchKernelGGL(fwd_gather_kernel, dim3(gx, 1), blk, 0, st, g, p.d_slots.as<Slot>(), sl,
                            p.w_H.as<double>(), p.w_Y.as<double>(), p.w_X.as<double>());
         OSHT_HIP(hipGetLastError());
         gemm_slots(p, kFwd, sl, sl + 1, st);
+        gemm_slots(p, kFwdAlias, sl, sl + 1, st);
       }
     }
   }
@@ -389,7 +426,7 @@ void run_forward_adjoint(Plan& p, const double* flmbar, double* fbar, int64_t B,
       OSHT_HIP(hipGetLastError());
     }
   }
-  launch_ring_synthesis(p, p.w_H.as<double>(), 1, nullptr, fbar, B, st);
+  launch_ring_synthesis(p, p.w_H.as<double>(), 1, fbar, B, st);
 }
 
 void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {

@@ -49,7 +49,9 @@ __device__ __forceinline__ int64_t alias_index(const Geo& g, const Slot* __restr
 }
 
 
-enum { kInv = 0, kFwd = 1, kIadj = 2, kFadj = 3, kCorr = 4, kNumDir = 5 };
+// GEMM directions; kFwdAlias / kCorrAlias carry the alias rows of Q_m
+// separately in FP32 plans (empty otherwise).
+enum { kInv = 0, kFwd = 1, kIadj = 2, kFadj = 3, kCorr = 4, kFwdAlias = 5, kCorrAlias = 6, kNumDir = 7 };
 
 void ensure_workspace(Plan& p, int64_t B);
 void launch_fwd_scatter(const Plan& p, const double* Y, double* flm, int64_t B, hipStream_t st);
