@@ -39,7 +39,7 @@ def test_strerror_and_codes():
 
 
 @pytest.mark.parametrize("L,spin,flags", [(0, 0, 0), (-3, 0, 0), (5000, 0, 0), (8, 8, 0), (8, -9, 0),
-                                          (8, 0, 0x100), (8, 0, 0x20)])
+                                          (8, 0, 0x200), (8, 0, 0x20)])
 def test_plan_create_rejects_bad_arguments(L, spin, flags):
     lib = _lib()
     h = ctypes.c_void_p()
