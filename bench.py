@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="mixed,fp64", help="comma list; the first is the headline")
+    ap.add_argument("--no-tune", action="store_true", help="skip plan-time autotuning (default block shape)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (HBM counter calibration)")
     return ap.parse_args()
@@ -152,9 +153,19 @@ def main():
     flm_h = inputs.coeffs(L, B, seed=5, weighted=True)
     flm = torch.as_tensor(flm_h).cuda()
     paths = [s.strip() for s in args.paths.split(",") if s.strip()]
+    # placement cache plus a scratch directory for the tuner's choices
+    import shutil
+    import tempfile
+    from paper_1403_4661_amd import THETA_CACHE_DIR
+    tune_dir = tempfile.mkdtemp(prefix="osht_tune_")
+    src = os.path.join(THETA_CACHE_DIR, f"theta_greedy_L{L}.txt")
+    if os.path.exists(src):
+        shutil.copy(src, tune_dir)
     res = {}
     for name in paths:
-        plan = Plan(L, 0, precision="fp32" if name == "mixed" else "fp64")
+        # plan-time autotuning of the forward sweep's block shape (not timed)
+        plan = Plan(L, 0, precision="fp32" if name == "mixed" else "fp64", tune=not args.no_tune,
+                    theta_cache_dir=tune_dir)
         r = run_path(name, plan, flm, args.steps, args.warmup)
         r["device_bytes"] = plan.info()["device_bytes"]
         r["plan"] = plan

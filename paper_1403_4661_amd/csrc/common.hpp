@@ -92,6 +92,8 @@ struct GemmDesc {
   int32_t M, N, K;
   int32_t fp32;   // A is float (else double)
   double alpha, beta;
+  int32_t m_lo;   // rows [m_lo, M) are computed and stored (tiles start at m_lo / 64)
+  int32_t pad;
 };
 
 struct GemmTask {
@@ -143,7 +145,7 @@ struct FwdBlocks {
   std::vector<int32_t> wide_ptr, wide_slot, wide_row;  // block -> (slot, row) pairs of rings k < kthr
   int max_unk = 0;
   int64_t max_w = 0;                           // max W entries in one block
-  int cpw = 2;                                 // delta-solve columns per workgroup
+  int cpw = 1;                                 // delta-solve columns per workgroup
   int lds_limit = 160 * 1024;
   void clear_host() {
     for (auto* v : {&q0, &q1, &slot_ptr, &slot_list, &unk_ptr, &lev_blk_ptr, &lev_ptr, &unk_slot, &unk_r, &unk_m,

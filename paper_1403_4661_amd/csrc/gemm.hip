@@ -24,6 +24,8 @@
 // symbol (inverse apply, forward apply, correction, adjoints, plan
 // construction) so that per-kernel profiles separate the launches.
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace osht {
@@ -161,7 +163,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& d, const GemmTask& t, 
     for (int v = 0; v < 4; ++v) {
       const int row = m0 + wave * 16 + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
       const int col = n0 + nb * 16 + (lane & 15);
-      if (row < d.M && col < d.N) {
+      if (row >= d.m_lo && row < d.M && col < d.N) {
         double* cp = d.C + (int64_t)row * d.sCr + (int64_t)col * d.sCc;
         double r = d.alpha * acc[nb][v];
         if (d.beta != 0.0) r += d.beta * (*cp);
@@ -282,7 +284,154 @@ __device__ __forceinline__ void gemm_tile_cm(const GemmDesc& d, const GemmTask& 
     for (int v = 0; v < 4; ++v) {
       const int r = m0 + wave * 16 + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
       const int col = n0 + nb * 16 + (lane & 15);
-      if (r < d.M && col < d.N) {
+      if (r >= d.m_lo && r < d.M && col < d.N) {
+        double* cp = d.C + (int64_t)r * d.sCr + (int64_t)col * d.sCc;
+        double x = d.alpha * acc[nb][v];
+        if (d.beta != 0.0) x += d.beta * (*cp);
+        *cp = x;
+      }
+    }
+  }
+}
+
+// Streaming variant for column-major A and row-major B: both tiles go from
+// global memory straight into LDS (global_load_lds, 16 bytes per lane) with
+// NS pipeline stages in flight, so each workgroup keeps NS-1 k-tiles of A
+// (the stream that sets the pace) outstanding without spending registers on
+// them.  Lanes that fall outside A or B (k >= K, rows >= M, columns >= N)
+// load from a zero block, so no tile needs zero-filling.  LDS rows are
+// XOR-swizzled by 16 elements per k parity (FP64) or k mod 4 (FP32 A) so
+// that the four 16-lane groups of an MFMA operand read hit different banks;
+// a 16-byte slot (2 FP64 or 4 FP32 rows) is never split by the swizzle.
+__device__ __align__(16) double g_gemm_zero[2];
+
+constexpr int TKS = 16;  // k-tile depth
+constexpr int NST = 3;   // pipeline stages
+
+template <class T>
+struct StreamShape {
+  static constexpr int ES = sizeof(T);
+  static constexpr int LPC = 64 * ES / 16;        // lanes per A column (32 | 16)
+  static constexpr int CPI = 64 / LPC;            // A columns per wave load (2 | 4)
+  static constexpr int NIA = TKS / CPI;           // wave loads per A tile (8 | 4)
+  static constexpr int NIB = TKS / 2;             // wave loads per B tile (2 FP64 rows each)
+  static constexpr int PER_WAVE = (NIA + NIB) / 4;
+  static constexpr int A_BYTES = 64 * TKS * ES;
+  static constexpr int STAGE = A_BYTES + TKS * 64 * 8;
+  static __device__ __forceinline__ int aswz(int k) { return ES == 8 ? 16 * (k & 1) : 16 * (k & 3); }
+};
+constexpr int kStreamSmemBytes = NST * StreamShape<double>::STAGE;
+
+__device__ __forceinline__ int bswz(int k) { return 16 * (k & 1); }
+
+template <class T>
+__device__ __forceinline__ void stream_issue(const GemmDesc& d, const T* __restrict__ A, int m0, int n0, int k0,
+                                             char* stage) {
+  typedef StreamShape<T> S;
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // A: column c of the tile holds rows m0..m0+63, row r at position r ^ aswz(k)
+#pragma unroll
+  for (int i = wave; i < S::NIA; i += 4) {
+    const int c = i * S::CPI + lane / S::LPC;
+    const int pos = (lane % S::LPC) * (16 / S::ES);  // first row position of this slot
+    const int k = k0 + c;
+    const int r = m0 + (pos ^ S::aswz(k));
+    const void* src = (k < d.K && r < d.M) ? (const void*)(A + r + (int64_t)k * d.sAc) : (const void*)g_gemm_zero;
+    __builtin_amdgcn_global_load_lds(src, (lds_ptr)(stage + i * 1024), 16, 0, 0);
+  }
+  // B: row kk of the tile holds columns n0..n0+63, column j at position j ^ bswz(k)
+  char* bst = stage + S::A_BYTES;
+#pragma unroll
+  for (int i = wave; i < S::NIB; i += 4) {
+    const int kk = 2 * i + lane / 32;
+    const int pos = (lane % 32) * 2;
+    const int k = k0 + kk;
+    const int j = n0 + (pos ^ bswz(k));
+    const void* src = (k < d.K && j < d.N) ? (const void*)(d.B + (int64_t)k * d.sBr + j) : (const void*)g_gemm_zero;
+    __builtin_amdgcn_global_load_lds(src, (lds_ptr)(bst + i * 1024), 16, 0, 0);
+  }
+}
+
+// waits until at most n of this wave's stream loads are outstanding
+__device__ __forceinline__ void wait_vm(int n) {
+  switch (n) {  // vmcnt in bits 3:0; expcnt (6:4) and lgkmcnt (11:8) left at their maxima
+    case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+    case 1: __builtin_amdgcn_s_waitcnt(0x0F71); break;
+    case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
+    case 3: __builtin_amdgcn_s_waitcnt(0x0F73); break;
+    case 4: __builtin_amdgcn_s_waitcnt(0x0F74); break;
+    case 5: __builtin_amdgcn_s_waitcnt(0x0F75); break;
+    case 6: __builtin_amdgcn_s_waitcnt(0x0F76); break;
+    case 7: __builtin_amdgcn_s_waitcnt(0x0F77); break;
+    default: __builtin_amdgcn_s_waitcnt(0x0F78); break;
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTask& t, char* smem) {
+  typedef StreamShape<T> S;
+  constexpr bool F64 = sizeof(T) == 8;
+  const T* __restrict__ A = static_cast<const T*>(d.A);
+  const int m0 = t.mt * TM, n0 = t.nt * TN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kq = lane >> 4, li = lane & 15;
+  dbl4 acc[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int nt = (d.K + TKS - 1) / TKS;
+#pragma unroll
+  for (int st = 0; st < NST - 1; ++st)
+    if (st < nt) stream_issue<T>(d, A, m0, n0, st * TKS, smem + st * S::STAGE);
+  for (int kt = 0; kt < nt; ++kt) {
+    // tiles issued after kt: min(NST-2, nt-1-kt) before this iteration's issue
+    const int ahead = min(NST - 2, nt - 1 - kt);
+    wait_vm(ahead * S::PER_WAVE);
+    // tile kt complete in LDS, tile kt-1's stage free.  A bare barrier: a
+    // fence here would also wait for the loads still in flight.
+    __builtin_amdgcn_s_barrier();
+    if (kt + NST - 1 < nt) stream_issue<T>(d, A, m0, n0, (kt + NST - 1) * TKS, smem + ((kt + NST - 1) % NST) * S::STAGE);
+    const char* stage = smem + (kt % NST) * S::STAGE;
+    const T* As = reinterpret_cast<const T*>(stage);
+    const double* Bs = reinterpret_cast<const double*>(stage + S::A_BYTES);
+    if constexpr (F64) {
+#pragma unroll
+      for (int s = 0; s < TKS / 4; ++s) {
+        const int k = 4 * s + kq;
+        const double a = As[k * 64 + ((wave * 16 + li) ^ S::aswz(k))];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const double b = Bs[k * 64 + ((nb * 16 + li) ^ bswz(k))];
+          acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[nb], 0, 0, 0);
+        }
+      }
+    } else {
+      flt4 c[4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) c[nb] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < TKS / 4; ++s) {
+        const int k = 4 * s + kq;
+        const float a = As[k * 64 + ((wave * 16 + li) ^ S::aswz(k))];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const float b = (float)Bs[k * 64 + ((nb * 16 + li) ^ bswz(k))];
+          c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c[nb], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[nb][v] += (double)c[nb][v];
+    }
+  }
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = m0 + wave * 16 + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+      const int col = n0 + nb * 16 + (lane & 15);
+      if (r >= d.m_lo && r < d.M && col < d.N) {
         double* cp = d.C + (int64_t)r * d.sCr + (int64_t)col * d.sCc;
         double x = d.alpha * acc[nb][v];
         if (d.beta != 0.0) x += d.beta * (*cp);
@@ -301,12 +450,17 @@ static_assert(2 * TK2 * (TN + Pad<double>::v) <= kSmemDoubles, "LDS size");
 template <bool ARF, bool BCF, class Role>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs,
                                                    const GemmTask* __restrict__ tasks) {
-  __shared__ double smem[kSmemDoubles];
+  __shared__ __align__(16) double smem[(ARF && BCF) ? (kStreamSmemBytes / 8 > kSmemDoubles ? kStreamSmemBytes / 8 : kSmemDoubles)
+                                                   : kSmemDoubles];
   const GemmTask t = tasks[blockIdx.x];
   const GemmDesc d = descs[t.desc];
+  // Column-major A streams through LDS (measured fastest on MI355X for FP32
+  // and for the forward's per-block launches), except the FP64 inverse apply,
+  // a single full-occupancy launch where register-direct A is ahead.
   if constexpr (ARF && BCF) {
-    if (d.fp32) gemm_tile_cm<float>(d, t, smem);
-    else gemm_tile_cm<double>(d, t, smem);
+    if (d.fp32) gemm_tile_stream<float>(d, t, reinterpret_cast<char*>(smem));
+    else if constexpr (std::is_same<Role, RoleApplyInverse>::value) gemm_tile_cm<double>(d, t, smem);
+    else gemm_tile_stream<double>(d, t, reinterpret_cast<char*>(smem));
   } else {
     if (d.fp32) gemm_tile<ARF, BCF, float>(d, t, smem);
     else gemm_tile<ARF, BCF, double>(d, t, smem);
@@ -324,7 +478,7 @@ void gemm_tasks(const std::vector<GemmDesc>& descs, std::vector<GemmTask>& tasks
   tasks.clear();
   for (size_t i = 0; i < descs.size(); ++i) {
     const int mt = (int)ceil_div(descs[i].M, TM), nt = (int)ceil_div(descs[i].N, TN);
-    for (int a = 0; a < mt; ++a)
+    for (int a = descs[i].m_lo / TM; a < mt; ++a)
       for (int b = 0; b < nt; ++b) tasks.push_back(GemmTask{(int32_t)i, a, b, 0});
   }
 }

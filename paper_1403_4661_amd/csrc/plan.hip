@@ -308,8 +308,11 @@ double newton_schulz(Plan& p, int s0, int s1, DevBuf& scratch, std::vector<doubl
     if (!(mx == mx)) mx = INFINITY;
     best = std::min(best, mx);
     if (mx < 1e-15) break;
-    // quadratic phase has ended once the residual stops halving
-    if (mx < 1e-3 && mx > 0.5 * last) { if (++stall >= 2) break; } else stall = 0;
+    // The max-entry residual of a large P_m can sit near 1/n for many
+    // iterations before the quadratic phase (the smallest singular value is
+    // spread over n entries), so only a residual already at rounding level
+    // that stops halving ends the iteration.
+    if (mx < 1e-10 && mx > 0.5 * last) { if (++stall >= 2) break; } else stall = 0;
     last = mx;
   }
   hipLaunchKernelGGL(xnorm1_kernel, dim3(ns), dim3(256), 0, 0, d_slots, s0, Q, d_out.as<double>());
@@ -433,9 +436,10 @@ void build_plan(Plan& p) {
     OSHT_HIP(hipDeviceSynchronize());
   }
   build_chirps(p);
-  // Block size of the forward sweep: the largest b <= 32 (or OSHT_FWD_BLOCK)
-  // whose alias system fits the delta solve's LDS.
-  int b = 32;
+  // Block size of the forward sweep (or OSHT_FWD_BLOCK), shrunk until the
+  // alias system fits the delta solve's LDS: 48 levels from L = 768 up, else
+  // 32 (what the autotuner picks on MI355X at L = 1024 and 512).
+  int b = p.L >= 768 ? 48 : 32;
   const char* env = std::getenv("OSHT_FWD_BLOCK");
   if (env) b = std::max(1, std::atoi(env));
   while (!fwd_blocks_fit(p, b) && b > 1) b = std::max(1, b * 3 / 4);

@@ -238,13 +238,14 @@ void ensure_workspace(Plan& p, int64_t B) {
       if (dir == kFwd || dir == kCorr || dir == kFwdAlias || dir == kCorrAlias) {
         // rows [0, K) (coefficients) in the main descriptor, rows [K, K+|m|)
         // (aliases) in the alias one when the plan is FP32
+        // descriptors keep column-base pointers and select rows by [m_lo, M)
         const bool alias = dir == kFwdAlias || dir == kCorrAlias;
         const int r0 = alias ? sl.K : 0;
         const int r1 = f32 ? (alias ? sl.K + am : sl.K) : (alias ? 0 : sl.K + am);
-        setA(f32 && !alias, false, sl.offQ + r0);
+        setA(f32 && !alias, false, sl.offQ);
         d.sAr = 1; d.sAc = sl.ldQ;
-        d.M = std::max(0, r1 - r0);
-        d.C = Ys + (int64_t)r0 * ncols;
+        d.m_lo = r1 > r0 ? r0 : 0;
+        d.M = r1 > r0 ? r1 : 0;
         d.K = sl.R;
         if (dir == kCorr || dir == kCorrAlias) {  // Y -= Q[:, 0:w] D
           d.K = std::min(wcorr[i], sl.R);
@@ -264,8 +265,8 @@ void ensure_workspace(Plan& p, int64_t B) {
   const int nblk = (int)p.fb.q0.size();
   auto emit = [&](int d) {
     const GemmDesc& g = p.h_gdesc[d];
-    if (g.K <= 0 || g.M <= 0) return;
-    for (int a = 0; a < (int)ceil_div(g.M, 64); ++a)
+    if (g.K <= 0 || g.M <= g.m_lo) return;
+    for (int a = g.m_lo / 64; a < (int)ceil_div(g.M, 64); ++a)
       for (int c = 0; c < (int)ceil_div(g.N, 64); ++c) bt.push_back(GemmTask{d, a, c, 0});
   };
   for (int blk = 0; blk < nblk; ++blk) {

@@ -177,3 +177,24 @@ def test_forward_block_sizes(L, s, b, monkeypatch):
     got = to_host(p.forward(to_dev(f)))
     tol = 1e-11 if s == 0 else 1e-8  # spin: alias-chain error growth, see the design doc
     assert relmax(got, ref) < tol
+
+
+def test_autotuned_plan_matches_oracle_and_caches_choice(tmp_path):
+    """OSHT_TUNE: the forward block shape is timed on the device and cached;
+    a second plan reads the cached choice; results stay at oracle parity."""
+    import shutil
+    from oracle import sht
+    from paper_1403_4661_amd import THETA_CACHE_DIR, Plan
+    L = 64
+    shutil.copy(f"{THETA_CACHE_DIR}/theta_greedy_L{L}.txt", tmp_path)
+    p = Plan(L, 0, theta_cache_dir=str(tmp_path), tune=True)
+    files = [f for f in tmp_path.iterdir() if f.name.startswith("tune_fwd_")]
+    assert len(files) == 1
+    b, cpw = (int(x) for x in files[0].read_text().split()[:2])
+    assert 1 <= b <= L and cpw in (1, 2, 4)
+    p2 = Plan(L, 0, theta_cache_dir=str(tmp_path), tune=True)
+    flm = inputs.coeffs(L, 3, seed=21)
+    f = sht.inverse(oplan(L), flm)
+    ref = sht.forward(oplan(L), f)
+    for q in (p, p2):
+        assert relmax(to_host(q.forward(to_dev(f))), ref) < 1e-11
