@@ -45,7 +45,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="mixed,fp64", help="comma list; the first is the headline")
-    ap.add_argument("--no-tune", action="store_true", help="skip plan-time autotuning (default block shape)")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the forward block shape at plan time (default: the built-in shape, which is "
+                         "what the tuner picks for L=1024 on MI355X)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (HBM counter calibration)")
     return ap.parse_args()
@@ -105,10 +107,53 @@ def cpu_baseline(L_metric):
 
 
 def forward_apply_flops(L, B):
-    """Algorithmic flops of the forward apply: order |m| streams the
-    L x (L-|m|) matrix [P^-1; A^top P^-1] against 4B real columns (spin 0
-    pairs +-m), 2 flops per entry and column."""
-    return sum(8.0 * B * L * (L - am) for am in range(L))
+    """Algorithmic flops of the forward apply, split by the precision of the
+    matrix rows: order |m| streams the L x (L-|m|) matrix
+    [P^-1; A^top P^-1] against 4B real columns (spin 0 pairs +-m), 2 flops
+    per entry and column; the (L-|m|) x (L-|m|) block P^-1 is FP32 on the
+    mixed path, the |m| x (L-|m|) alias block A^top P^-1 always FP64.
+    Returns (coefficient-row flops, alias-row flops)."""
+    coef = sum(8.0 * B * (L - am) * (L - am) for am in range(L))
+    alias = sum(8.0 * B * am * (L - am) for am in range(L))
+    return coef, alias
+
+
+def apply_peak(path, coef, alias):
+    """Matrix-core peak of the forward apply: FP64 78.6 TFLOP/s; on the mixed
+    path the flop-weighted combination of FP32 (157.3) for the coefficient
+    rows and FP64 (78.6) for the alias rows, i.e. total flops over the time
+    both parts would take at their peaks."""
+    if path == "fp64":
+        return PEAK_TFLOPS["fp64"]
+    return (coef + alias) / (coef / PEAK_TFLOPS["mixed"] + alias / PEAK_TFLOPS["fp64"])
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_forward_L1024_B16.md")
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_1403_4661_amd", "csrc", f) for f in ("gemm.hip", "transform.hip", "sweep.hip")]
+
+
+def measured_traffic(path, L, B, launches_per_step):
+    """HBM bytes per launch of the forward apply from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on this path,
+    workload and block count with the current kernel sources; else None."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(f, "rb").read())
+    rec = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].strip().split(": ", 1)
+            rec[k.strip("`")] = v.strip("`")
+    try:
+        if (rec.get("sources_sha256") != h.hexdigest() or rec.get("path") != path or int(rec.get("L", 0)) != L
+                or int(rec.get("batch", 0)) != B or int(rec.get("launches_per_step", 0)) != launches_per_step):
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def run_path(name, plan, flm, steps, warmup):
@@ -163,8 +208,8 @@ def main():
         shutil.copy(src, tune_dir)
     res = {}
     for name in paths:
-        # plan-time autotuning of the forward sweep's block shape (not timed)
-        plan = Plan(L, 0, precision="fp32" if name == "mixed" else "fp64", tune=not args.no_tune,
+        # optional plan-time autotuning of the forward sweep's block shape (not timed)
+        plan = Plan(L, 0, precision="fp32" if name == "mixed" else "fp64", tune=args.tune,
                     theta_cache_dir=tune_dir)
         r = run_path(name, plan, flm, args.steps, args.warmup)
         r["device_bytes"] = plan.info()["device_bytes"]
@@ -178,7 +223,8 @@ def main():
     out_paths = {}
     for name, r in res.items():
         ms_step = r["seconds"] / args.steps * 1e3
-        ach = forward_apply_flops(L, B) * args.steps / (r["apply_forward_ms"] * 1e-3) / 1e12 \
+        coef, alias = forward_apply_flops(L, B)
+        ach = (coef + alias) * args.steps / (r["apply_forward_ms"] * 1e-3) / 1e12 \
             if r["apply_forward_ms"] > 0 else 0.0
         out_paths[name] = {
             "sht_per_s": B * args.steps / r["seconds"],
@@ -186,7 +232,7 @@ def main():
             "max_rel_err_roundtrip": rel(r["g"], flm),
             "device_bytes": r["device_bytes"],
             "apply_forward": {"launches": r["apply_forward_launches"], "ms_total": r["apply_forward_ms"],
-                              "tflops": ach},
+                              "tflops": ach, "peak_tflops": apply_peak(name, coef, alias)},
         }
     if "fp64" in res and len(res) > 1:
         for name in res:
@@ -209,10 +255,11 @@ def main():
         inv_err = max(inv_err, float(np.max(np.abs(got - v)) / np.max(np.abs(v))))
 
     hp = out_paths[head]
-    peak = PEAK_TFLOPS[head]
+    peak = hp["apply_forward"]["peak_tflops"]
     roof = {"bound": "mfma", "kernel": "gemm_kernel<..., RoleApplyForward> (apply_forward)",
             "achieved": hp["apply_forward"]["tflops"], "peak": peak, "unit": "TFLOP/s",
-            "frac": hp["apply_forward"]["tflops"] / peak, "traffic": None}
+            "frac": hp["apply_forward"]["tflops"] / peak,
+            "traffic": measured_traffic(head, L, B, hp["apply_forward"]["launches"] // args.steps)}
     out = {
         "metric": "fwd+inv SHT/s at L=1024, batch 16 (mixed vs FP64, max rel err); HBM GB/s",
         "value": hp["sht_per_s"],

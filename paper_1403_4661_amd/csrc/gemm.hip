@@ -452,7 +452,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
                                                    const GemmTask* __restrict__ tasks) {
   __shared__ __align__(16) double smem[(ARF && BCF) ? (kStreamSmemBytes / 8 > kSmemDoubles ? kStreamSmemBytes / 8 : kSmemDoubles)
                                                    : kSmemDoubles];
-  const GemmTask t = tasks[blockIdx.x];
+  // Workgroups are dispatched round-robin over the 8 XCDs.  Tasks come in
+  // descriptor order, the M tiles of one descriptor (which share its B panel)
+  // adjacent; runs of 16 consecutive tasks go to workgroups of one XCD, so a
+  // panel is fetched into one L2, while successive runs rotate over the XCDs
+  // (descriptors of very different sizes stay balanced).  Bijective on
+  // [0, gridDim.x); the tail round uses the plain block split.
+  constexpr int C = 16, RND = 8 * C;
+  const int G = gridDim.x, b = blockIdx.x, base = (b / RND) * RND, p = b - base;
+  int ti;
+  if (base + RND <= G) {
+    ti = base + (p & 7) * C + (p >> 3);
+  } else {
+    const int S = G - base, q = S >> 3, r = S & 7, x = p & 7, l = p >> 3;
+    ti = base + (x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l);
+  }
+  const GemmTask t = tasks[ti];
   const GemmDesc d = descs[t.desc];
   // Column-major A streams through LDS (measured fastest on MI355X for FP32
   // and for the forward's per-block launches), except the FP64 inverse apply,
