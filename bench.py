@@ -5,9 +5,11 @@ One step = one inverse SHT followed by one forward SHT of a batch of B maps
 spin 0, L = 1024, B = 16, coefficients N(0,1)(1+l)^-1 (seed 5).
 
 Two paths run on the same inputs, each timed over its own K steps:
-  mixed  FP32 plan: FP32 matrix-core applies of A_m and P_m^{-1}; the alias
-         rows of the forward sweep, ring DFTs and all buffers FP64;
-  fp64   FP64 throughout.
+  mixed      FP32 plan: the inverse apply on FP32 A_m with FP32 matrix cores;
+             the forward sweep, ring DFTs and all buffers FP64;
+  fp64       FP64 throughout;
+  (mixed-fwd, optional: also the forward's P_m^{-1} rows on FP32 matrix
+             cores, alias rows FP64.)
 `value` is the mixed path's SHT/s; the fp64 path, the speedup and the
 errors of both paths are reported beside it.
 
@@ -33,7 +35,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}  # MI355X dense matrix FP64 / FP32
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X dense matrix FP64 / FP32
+PRECISION = {"mixed": "fp32", "mixed-fwd": "fp32-fwd", "fp64": "fp64"}
 
 
 def parse():
@@ -119,13 +122,13 @@ def forward_apply_flops(L, B):
 
 
 def apply_peak(path, coef, alias):
-    """Matrix-core peak of the forward apply: FP64 78.6 TFLOP/s; on the mixed
-    path the flop-weighted combination of FP32 (157.3) for the coefficient
-    rows and FP64 (78.6) for the alias rows, i.e. total flops over the time
-    both parts would take at their peaks."""
-    if path == "fp64":
+    """Matrix-core peak of the forward apply: FP64 78.6 TFLOP/s; with FP32
+    coefficient rows (mixed-fwd) the flop-weighted combination of FP32
+    (157.3) for those rows and FP64 (78.6) for the alias rows, i.e. total
+    flops over the time both parts would take at their peaks."""
+    if path != "mixed-fwd":
         return PEAK_TFLOPS["fp64"]
-    return (coef + alias) / (coef / PEAK_TFLOPS["mixed"] + alias / PEAK_TFLOPS["fp64"])
+    return (coef + alias) / (coef / PEAK_TFLOPS["fp32"] + alias / PEAK_TFLOPS["fp64"])
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_forward_L1024_B16.md")
@@ -209,7 +212,7 @@ def main():
     res = {}
     for name in paths:
         # optional plan-time autotuning of the forward sweep's block shape (not timed)
-        plan = Plan(L, 0, precision="fp32" if name == "mixed" else "fp64", tune=args.tune,
+        plan = Plan(L, 0, precision=PRECISION[name], tune=args.tune,
                     theta_cache_dir=tune_dir)
         r = run_path(name, plan, flm, args.steps, args.warmup)
         r["device_bytes"] = plan.info()["device_bytes"]
@@ -271,7 +274,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 apply + f64" if head == "mixed" else "f64",
+        "dtype": {"mixed": "f32 inverse apply + f64", "mixed-fwd": "f32 applies + f64"}.get(head, "f64"),
         "data": "synthetic",
         "config": {"workload": f"spin-0 inverse then forward SHT, L={L}, batch {B}, flm N(0,1)(1+l)^-1 seed 5",
                    "L": L, "batch": B, "spin": 0, "path": head, "parallelism": "single-gpu"},

@@ -51,10 +51,15 @@ extern "C" {
  * Legendre/Wigner recursion, the inversion of every P_m, the ring DFTs, the
  * alias gathers and every buffer the caller sees stay FP64 in all modes. */
 #define OSHT_PREC_FP64        0x0u   /* FP64 throughout */
-#define OSHT_PREC_FP32        0x1u   /* matrices A_m and [P_m^-1; A_m^top P_m^-1] built in FP64,
-                                        then stored rounded to FP32; applied on FP32 matrix cores
-                                        with FP32 accumulation over 16-term k-slices summed in FP64;
-                                        the RHS is rounded to FP32 as it is staged */
+#define OSHT_PREC_FP32        0x1u   /* A_m built and checked in FP64, stored rounded to FP32 and
+                                        applied on FP32 matrix cores (inverse and inverse adjoint):
+                                        FP32 accumulation over 16-term k-slices summed in FP64,
+                                        right-hand side rounded to FP32 as it is read.  The forward
+                                        sweep stays FP64 (its descending-order alias chain amplifies
+                                        rounding). */
+#define OSHT_PREC_FP32_FWD    0x2u   /* OSHT_PREC_FP32, and the forward's coefficient rows P_m^{-1}
+                                        also on FP32 matrix cores; its alias rows A_m^top P_m^{-1}
+                                        stay FP64 */
 #define OSHT_PREC_MASK        0x0fu
 /* colatitude placement (Sec. III-D) */
 #define OSHT_THETA_GREEDY       0x00u  /* condition-number-minimising greedy */

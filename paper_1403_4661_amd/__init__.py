@@ -48,17 +48,20 @@ class Plan:
 
     def __init__(self, L, spin=0, placement="greedy", precision="fp64", theta_cache_dir=THETA_CACHE_DIR,
                  device=None, tune=False):
-        """precision: "fp64" (FP64 throughout) or "fp32" (FP32 matrix-core
-        applies of A_m and P_m^{-1}; alias rows, DFTs and buffers FP64).
+        """precision: "fp64" (FP64 throughout), "fp32" (inverse and its
+        adjoint on FP32 A_m with FP32 matrix cores; the forward sweep, DFTs
+        and buffers FP64) or "fp32-fwd" (also the forward's P_m^{-1} rows in
+        FP32; its alias rows stay FP64).
         tune: time the forward sweep's block shapes on this device and keep
         the fastest (cached in theta_cache_dir)."""
         import torch
 
         if placement not in ("greedy", "alternating"):
             raise ValueError("placement must be 'greedy' or 'alternating'")
-        if precision not in ("fp64", "fp32"):
-            raise ValueError("precision must be 'fp64' or 'fp32'")
-        flags = (_lib.OSHT_PREC_FP64 if precision == "fp64" else _lib.OSHT_PREC_FP32) | (
+        prec = {"fp64": _lib.OSHT_PREC_FP64, "fp32": _lib.OSHT_PREC_FP32, "fp32-fwd": _lib.OSHT_PREC_FP32_FWD}
+        if precision not in prec:
+            raise ValueError("precision must be 'fp64', 'fp32' or 'fp32-fwd'")
+        flags = prec[precision] | (
             _lib.OSHT_THETA_GREEDY if placement == "greedy" else _lib.OSHT_THETA_ALTERNATING) | (
             _lib.OSHT_TUNE if tune else 0)
         self.L, self.spin, self.precision = int(L), int(spin), precision

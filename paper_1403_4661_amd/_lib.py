@@ -21,6 +21,7 @@ OSHT_EIO = -6
 
 OSHT_PREC_FP64 = 0x0
 OSHT_PREC_FP32 = 0x1
+OSHT_PREC_FP32_FWD = 0x2
 OSHT_THETA_GREEDY = 0x00
 OSHT_THETA_ALTERNATING = 0x10
 OSHT_TUNE = 0x100

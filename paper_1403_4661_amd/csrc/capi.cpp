@@ -151,8 +151,8 @@ int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_di
   if (L < 1 || L > 4096) return fail(OSHT_EINVAL, "L must be in [1, 4096]");
   if (spin <= -L || spin >= L) return fail(OSHT_EINVAL, "|spin| must be < L");
   const uint32_t prec = flags & OSHT_PREC_MASK, theta = flags & OSHT_THETA_MASK;
-  if (prec != OSHT_PREC_FP64 && prec != OSHT_PREC_FP32)
-    return fail(OSHT_ENOTSUP, "precision must be OSHT_PREC_FP64 or OSHT_PREC_FP32");
+  if (prec != OSHT_PREC_FP64 && prec != OSHT_PREC_FP32 && prec != OSHT_PREC_FP32_FWD)
+    return fail(OSHT_ENOTSUP, "precision must be OSHT_PREC_FP64, OSHT_PREC_FP32 or OSHT_PREC_FP32_FWD");
   if (theta != OSHT_THETA_GREEDY && theta != OSHT_THETA_ALTERNATING) return fail(OSHT_EINVAL, "unknown placement flag");
   if (flags & ~(OSHT_PREC_MASK | OSHT_THETA_MASK | OSHT_TUNE)) return fail(OSHT_EINVAL, "unknown flag bits");
   osht_plan_t* h = nullptr;
@@ -162,7 +162,8 @@ int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_di
     p.L = L;
     p.spin = spin;
     p.flags = flags;
-    p.fp32 = prec == OSHT_PREC_FP32;
+    p.fp32 = prec == OSHT_PREC_FP32 || prec == OSHT_PREC_FP32_FWD;
+    p.fp32_fwd = prec == OSHT_PREC_FP32_FWD;
     if (theta_cache_dir) p.cache_dir = theta_cache_dir;
     OSHT_HIP(hipGetDevice(&p.device));
     p.numer.assign(L, 0);

@@ -141,6 +141,9 @@ struct FwdBlocks {
   std::vector<int64_t> w_ptr;                  // per unknown -> W entries
   std::vector<int32_t> w_col;                  // block-local unknown index
   std::vector<int64_t> w_idx;                  // element of d_Q holding the value
+  std::vector<int64_t> wt_ptr;                 // per unknown u': W^T entries (u, W_{u,u'}), for the adjoint
+  std::vector<int32_t> wt_row;                 // block-local u
+  std::vector<int64_t> wt_idx;                 // element of d_Q holding W_{u,u'}
   int kthr = 0;                                // rings k < kthr: wide gather
   std::vector<int32_t> wide_ptr, wide_slot, wide_row;  // block -> (slot, row) pairs of rings k < kthr
   int max_unk = 0;
@@ -149,14 +152,16 @@ struct FwdBlocks {
   int lds_limit = 160 * 1024;
   void clear_host() {
     for (auto* v : {&q0, &q1, &slot_ptr, &slot_list, &unk_ptr, &lev_blk_ptr, &lev_ptr, &unk_slot, &unk_r, &unk_m,
-                    &src_ptr, &src_slot, &src_row, &src_m, &w_col, &wide_ptr, &wide_slot, &wide_row})
+                    &src_ptr, &src_slot, &src_row, &src_m, &w_col, &wide_ptr, &wide_slot, &wide_row, &wt_row})
       v->clear();
     w_ptr.clear();
     w_idx.clear();
+    wt_ptr.clear();
+    wt_idx.clear();
     max_unk = 0;
   }
   DevBuf d_slot_list, d_lev_ptr, d_unk_slot, d_unk_r, d_unk_m, d_src_ptr, d_src_slot, d_src_row, d_src_m,
-      d_w_ptr, d_w_col, d_w_val, d_wide_slot, d_wide_row;
+      d_w_ptr, d_w_col, d_w_val, d_wide_slot, d_wide_row, d_wt_ptr, d_wt_row, d_wt_val;
 };
 
 struct Plan {
@@ -173,8 +178,9 @@ struct Plan {
   DevBuf d_cos, d_sin, d_cosh, d_sinh;
   DevBuf d_slots;
   DevBuf d_A, d_Q;            // FP64 blocks (FP32 plans release d_A and keep d_Q for the alias rows)
-  DevBuf d_A32, d_Q32;        // FP32 copies, same element offsets (FP32 plans)
-  bool fp32 = false;          // FP32 plan (see OSHT_PREC_FP32)
+  DevBuf d_A32, d_Q32;        // FP32 copies, same element offsets (d_Q32 for OSHT_PREC_FP32_FWD only)
+  bool fp32 = false;          // inverse-side applies on FP32 A_m (OSHT_PREC_FP32, OSHT_PREC_FP32_FWD)
+  bool fp32_fwd = false;      // forward coefficient rows on FP32 P_m^{-1} as well (OSHT_PREC_FP32_FWD)
   DevBuf d_rings, d_chirp, d_twiddle, d_chirp_tab;
   std::vector<int32_t> h_ring_logM;
   int max_logM = 0;
@@ -183,6 +189,8 @@ struct Plan {
   FwdBlocks fb;
   std::vector<int32_t> h_btask_ptr;   // per block: [fwd, corr, end) offsets into d_btask
   DevBuf d_btask;
+  std::vector<int32_t> h_atask_ptr;   // per block: [adjoint apply, adjoint corr, end) offsets into d_atask
+  DevBuf d_atask;
   DevBuf d_gdesc, d_gtask;    // GEMM descriptors for the transforms
   int64_t ws_batch = 0;
   int64_t ws_version = 0;     // bumped whenever workspace or descriptor tables change
@@ -249,6 +257,7 @@ bool fwd_blocks_fit(Plan& p, int b);
 // Plan::cache_dir when set
 void tune_forward_blocks(Plan& p);
 void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st);
+void run_forward_adjoint_blocked(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st);
 
 // placement (theta.cpp)
 int theta_greedy(int L, int32_t* num_out, double* kappa_out);

@@ -2,27 +2,34 @@
 //
 // C(M x N) = alpha * A(M x K) * B(K x N) + beta * C, with C and B in FP64
 // and A (the plan's matrix: A_m, Q_m or their transposes) in FP64 or FP32.
+// Rows [m_lo, M) of C are computed and stored.
 //
 // One workgroup (4 waves) computes a 64 x 64 tile of C for one descriptor;
 // wave w owns rows [16w, 16w+16) and all 64 columns as four 16 x 16 MFMA
-// accumulators.  A and B tiles (64 x 16 and 16 x 64) are staged through LDS;
-// global loads follow whichever stride is unit, so reads are coalesced for
-// both storage orders.  Out-of-range rows, columns and k are zero-filled, so
-// any M, N, K >= 0 is valid.
+// accumulators.  Two tile paths:
+//  * streaming (column-major A, row-major B: the applies and the forward's
+//    correction): A and B tiles go from global memory straight into LDS
+//    with several k-tiles in flight (see gemm_tile_stream);
+//  * staged (the plan's Newton-Schulz products and the adjoints, which read
+//    A transposed): tiles pass through registers into double-buffered LDS,
+//    loads following whichever stride is unit.
+// Out-of-range rows, columns and k contribute zero, so any M, N, K >= 0 is
+// valid.
 //
-// FP64 path: v_mfma_f64_16x16x4f64.  Lane l supplies A[l % 16][l / 16] and
+// FP64: v_mfma_f64_16x16x4f64.  Lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator register v of lane l holds
 // D[l / 16 + 4 v][l % 16].
-// FP32 path: v_mfma_f32_16x16x4f32 on A (stored FP32) and B rounded to FP32
-// when staged.  Same operand layout; accumulator register v of lane l holds
-// D[4 (l / 16) + v][l % 16].  Each 16-deep k-tile is accumulated in FP32 by
-// the matrix core and then added into an FP64 running sum, so the FP32
-// accumulation error is that of a 16-term sum whatever K is.
+// FP32: v_mfma_f32_16x16x4f32 on A (stored FP32) and B rounded to FP32 as it
+// is read.  Same operand layout; accumulator register v of lane l holds
+// D[4 (l / 16) + v][l % 16].  At most 16 k are accumulated in FP32 by the
+// matrix core before the partial sums are added into FP64 accumulators, so
+// the FP32 accumulation error is that of a 16-term sum whatever K is.
 //
 // The precision is chosen per descriptor (GemmDesc::fp32), so one launch
-// can mix FP32 and FP64 matrices.  The Role parameter only names the kernel
+// can mix FP32 and FP64 matrices.  The Role parameter names the kernel
 // symbol (inverse apply, forward apply, correction, adjoints, plan
-// construction) so that per-kernel profiles separate the launches.
+// construction), so that per-kernel profiles separate the launches, and
+// selects the streaming tile shape.
 
 #include <type_traits>
 
@@ -173,127 +180,6 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& d, const GemmTask& t, 
   }
 }
 
-// Column-major A (the applies and the correction): each wave reads its own
-// 16-row A fragments straight from global memory into registers in the
-// MFMA operand layout (lane l: row l % 16, k = l / 16 of each 4-deep step;
-// 16 consecutive rows are 128 contiguous bytes), so A never passes through
-// LDS.  B (shared by the four waves) is staged through double-buffered LDS.
-// k-tiles are 32 deep; the next tile's A fragments and B elements are loaded
-// into registers while the current tile's MFMAs run.
-constexpr int TK2 = 32;
-constexpr int EB2 = TK2 * TN / 256;  // B elements per thread per tile (8)
-
-template <class T>
-__device__ __forceinline__ void load_a_frag(const GemmDesc& d, const T* __restrict__ A, int row, int k0, int kq,
-                                            T* a) {
-#pragma unroll
-  for (int s = 0; s < TK2 / 4; ++s) {
-    const int k = k0 + 4 * s + kq;
-    a[s] = (row < d.M && k < d.K) ? A[row + (int64_t)k * d.sAc] : T(0);
-  }
-}
-
-template <class T>
-__device__ __forceinline__ void load_b2(const GemmDesc& d, int n0, int k0, T* rb) {
-#pragma unroll
-  for (int t = 0; t < EB2; ++t) {
-    const int j = threadIdx.x & 63, kk = (threadIdx.x >> 6) + 4 * t;
-    const int gk = k0 + kk, gj = n0 + j;
-    rb[t] = (gk < d.K && gj < d.N) ? T(d.B[(int64_t)gk * d.sBr + gj]) : T(0);
-  }
-}
-
-template <class T, int P>
-__device__ __forceinline__ void store_b2(T (*Bs)[TN + P], const T* rb) {
-#pragma unroll
-  for (int t = 0; t < EB2; ++t) Bs[(threadIdx.x >> 6) + 4 * t][threadIdx.x & 63] = rb[t];
-}
-
-template <class T>
-__device__ __forceinline__ void gemm_tile_cm(const GemmDesc& d, const GemmTask& t, void* smem) {
-  constexpr int P = Pad<T>::v;
-  constexpr bool F64 = sizeof(T) == 8;
-  typedef T RowB[TN + P];
-  RowB(*Bs)[TK2] = reinterpret_cast<RowB(*)[TK2]>(smem);  // [2][TK2][TN + P]
-  const T* __restrict__ A = static_cast<const T*>(d.A);
-  const int m0 = t.mt * TM, n0 = t.nt * TN;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row = m0 + wave * 16 + (lane & 15), kq = lane >> 4;
-  dbl4 acc[4];
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) acc[nb] = dbl4{0.0, 0.0, 0.0, 0.0};
-  T a[TK2 / 4], an[TK2 / 4], rb[EB2];
-  const int nt = (d.K + TK2 - 1) / TK2;
-  if (nt > 0) {
-    load_a_frag<T>(d, A, row, 0, kq, a);
-    load_b2<T>(d, n0, 0, rb);
-    store_b2<T, P>(Bs[0], rb);
-  }
-  __syncthreads();
-  for (int kt = 0; kt < nt; ++kt) {
-    const int p = kt & 1;
-    const bool more = kt + 1 < nt;
-    if (more) {
-      load_a_frag<T>(d, A, row, (kt + 1) * TK2, kq, an);
-      load_b2<T>(d, n0, (kt + 1) * TK2, rb);
-    }
-    if constexpr (F64) {
-#pragma unroll
-      for (int s = 0; s < TK2 / 4; ++s) {
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-          const double b = Bs[p][4 * s + kq][nb * 16 + (lane & 15)];
-          acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b, acc[nb], 0, 0, 0);
-        }
-      }
-    } else {
-      flt4 c[4];
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) c[nb] = flt4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int s = 0; s < TK2 / 4; ++s) {
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-          const float b = Bs[p][4 * s + kq][nb * 16 + (lane & 15)];
-          c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b, c[nb], 0, 0, 0);
-        }
-        if (s == TK2 / 8 - 1) {  // FP32 partial sums cover 16 k at most
-#pragma unroll
-          for (int nb = 0; nb < 4; ++nb) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[nb][v] += (double)c[nb][v];
-            c[nb] = flt4{0.f, 0.f, 0.f, 0.f};
-          }
-        }
-      }
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[nb][v] += (double)c[nb][v];
-    }
-    if (more) {
-      store_b2<T, P>(Bs[p ^ 1], rb);
-#pragma unroll
-      for (int s = 0; s < TK2 / 4; ++s) a[s] = an[s];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = m0 + wave * 16 + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
-      const int col = n0 + nb * 16 + (lane & 15);
-      if (r >= d.m_lo && r < d.M && col < d.N) {
-        double* cp = d.C + (int64_t)r * d.sCr + (int64_t)col * d.sCc;
-        double x = d.alpha * acc[nb][v];
-        if (d.beta != 0.0) x += d.beta * (*cp);
-        *cp = x;
-      }
-    }
-  }
-}
-
 // Streaming variant for column-major A and row-major B: both tiles go from
 // global memory straight into LDS (global_load_lds, 16 bytes per lane) with
 // NS pipeline stages in flight, so each workgroup keeps NS-1 k-tiles of A
@@ -308,26 +194,25 @@ __device__ __align__(16) double g_gemm_zero[2];
 constexpr int TKS = 16;  // k-tile depth
 constexpr int NST = 3;   // pipeline stages
 
-template <class T>
+template <class T, int TK = TKS>
 struct StreamShape {
   static constexpr int ES = sizeof(T);
   static constexpr int LPC = 64 * ES / 16;        // lanes per A column (32 | 16)
   static constexpr int CPI = 64 / LPC;            // A columns per wave load (2 | 4)
-  static constexpr int NIA = TKS / CPI;           // wave loads per A tile (8 | 4)
-  static constexpr int NIB = TKS / 2;             // wave loads per B tile (2 FP64 rows each)
+  static constexpr int NIA = TK / CPI;            // wave loads per A tile (8 | 4 at TK = 16)
+  static constexpr int NIB = TK / 2;              // wave loads per B tile (2 FP64 rows each)
   static constexpr int PER_WAVE = (NIA + NIB) / 4;
-  static constexpr int A_BYTES = 64 * TKS * ES;
-  static constexpr int STAGE = A_BYTES + TKS * 64 * 8;
+  static constexpr int A_BYTES = 64 * TK * ES;
+  static constexpr int STAGE = A_BYTES + TK * 64 * 8;
   static __device__ __forceinline__ int aswz(int k) { return ES == 8 ? 16 * (k & 1) : 16 * (k & 3); }
 };
-constexpr int kStreamSmemBytes = NST * StreamShape<double>::STAGE;
 
 __device__ __forceinline__ int bswz(int k) { return 16 * (k & 1); }
 
-template <class T>
+template <class T, int TK = TKS>
 __device__ __forceinline__ void stream_issue(const GemmDesc& d, const T* __restrict__ A, int m0, int n0, int k0,
                                              char* stage) {
-  typedef StreamShape<T> S;
+  typedef StreamShape<T, TK> S;
   typedef __attribute__((address_space(3))) void* lds_ptr;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // A: column c of the tile holds rows m0..m0+63, row r at position r ^ aswz(k)
@@ -353,24 +238,33 @@ __device__ __forceinline__ void stream_issue(const GemmDesc& d, const T* __restr
   }
 }
 
-// waits until at most n of this wave's stream loads are outstanding
+// waits until at most n (0..31) of this wave's stream loads are outstanding:
+// vmcnt in bits 3:0 and 15:14, expcnt (6:4) and lgkmcnt (11:8) at their maxima
+template <int N>
+__device__ __forceinline__ void wait_vm_c() {
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | 0x0F70);
+}
 __device__ __forceinline__ void wait_vm(int n) {
-  switch (n) {  // vmcnt in bits 3:0; expcnt (6:4) and lgkmcnt (11:8) left at their maxima
-    case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
-    case 1: __builtin_amdgcn_s_waitcnt(0x0F71); break;
-    case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
-    case 3: __builtin_amdgcn_s_waitcnt(0x0F73); break;
-    case 4: __builtin_amdgcn_s_waitcnt(0x0F74); break;
-    case 5: __builtin_amdgcn_s_waitcnt(0x0F75); break;
-    case 6: __builtin_amdgcn_s_waitcnt(0x0F76); break;
-    case 7: __builtin_amdgcn_s_waitcnt(0x0F77); break;
-    default: __builtin_amdgcn_s_waitcnt(0x0F78); break;
+  switch (n) {
+    case 0: wait_vm_c<0>(); break;
+    case 1: wait_vm_c<1>(); break;
+    case 2: wait_vm_c<2>(); break;
+    case 3: wait_vm_c<3>(); break;
+    case 4: wait_vm_c<4>(); break;
+    case 6: wait_vm_c<6>(); break;
+    case 8: wait_vm_c<8>(); break;
+    case 9: wait_vm_c<9>(); break;
+    case 12: wait_vm_c<12>(); break;
+    case 16: wait_vm_c<16>(); break;
+    case 18: wait_vm_c<18>(); break;
+    case 24: wait_vm_c<24>(); break;
+    default: wait_vm_c<0>(); break;
   }
 }
 
-template <class T>
+template <class T, int TK = TKS, int NS = NST>
 __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTask& t, char* smem) {
-  typedef StreamShape<T> S;
+  typedef StreamShape<T, TK> S;
   constexpr bool F64 = sizeof(T) == 8;
   const T* __restrict__ A = static_cast<const T*>(d.A);
   const int m0 = t.mt * TM, n0 = t.nt * TN;
@@ -379,24 +273,24 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
   dbl4 acc[4];
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) acc[nb] = dbl4{0.0, 0.0, 0.0, 0.0};
-  const int nt = (d.K + TKS - 1) / TKS;
+  const int nt = (d.K + TK - 1) / TK;
 #pragma unroll
-  for (int st = 0; st < NST - 1; ++st)
-    if (st < nt) stream_issue<T>(d, A, m0, n0, st * TKS, smem + st * S::STAGE);
+  for (int st = 0; st < NS - 1; ++st)
+    if (st < nt) stream_issue<T, TK>(d, A, m0, n0, st * TK, smem + st * S::STAGE);
   for (int kt = 0; kt < nt; ++kt) {
-    // tiles issued after kt: min(NST-2, nt-1-kt) before this iteration's issue
-    const int ahead = min(NST - 2, nt - 1 - kt);
+    // tiles issued after kt: min(NS-2, nt-1-kt) before this iteration's issue
+    const int ahead = min(NS - 2, nt - 1 - kt);
     wait_vm(ahead * S::PER_WAVE);
     // tile kt complete in LDS, tile kt-1's stage free.  A bare barrier: a
     // fence here would also wait for the loads still in flight.
     __builtin_amdgcn_s_barrier();
-    if (kt + NST - 1 < nt) stream_issue<T>(d, A, m0, n0, (kt + NST - 1) * TKS, smem + ((kt + NST - 1) % NST) * S::STAGE);
-    const char* stage = smem + (kt % NST) * S::STAGE;
+    if (kt + NS - 1 < nt) stream_issue<T, TK>(d, A, m0, n0, (kt + NS - 1) * TK, smem + ((kt + NS - 1) % NS) * S::STAGE);
+    const char* stage = smem + (kt % NS) * S::STAGE;
     const T* As = reinterpret_cast<const T*>(stage);
     const double* Bs = reinterpret_cast<const double*>(stage + S::A_BYTES);
     if constexpr (F64) {
 #pragma unroll
-      for (int s = 0; s < TKS / 4; ++s) {
+      for (int s = 0; s < TK / 4; ++s) {
         const int k = 4 * s + kq;
         const double a = As[k * 64 + ((wave * 16 + li) ^ S::aswz(k))];
 #pragma unroll
@@ -410,13 +304,21 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) c[nb] = flt4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int s = 0; s < TKS / 4; ++s) {
+      for (int s = 0; s < TK / 4; ++s) {
         const int k = 4 * s + kq;
         const float a = As[k * 64 + ((wave * 16 + li) ^ S::aswz(k))];
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
           const float b = (float)Bs[k * 64 + ((nb * 16 + li) ^ bswz(k))];
           c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c[nb], 0, 0, 0);
+        }
+        if (TK > 16 && s % 4 == 3 && s + 1 < TK / 4) {  // FP32 partial sums cover 16 k at most
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[nb][v] += (double)c[nb][v];
+            c[nb] = flt4{0.f, 0.f, 0.f, 0.f};
+          }
         }
       }
 #pragma unroll
@@ -444,14 +346,20 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
 // LDS of one tile pair: the FP64 layout is the larger one.
 constexpr int kSmemDoubles = 2 * 2 * TK * (TM + Pad<double>::v);
 static_assert(2 * TK * (TM + Pad<float>::v) * 2 * sizeof(float) <= kSmemDoubles * sizeof(double), "LDS size");
-static_assert(2 * TK2 * (TN + Pad<double>::v) <= kSmemDoubles, "LDS size");
+
+// Stream shape per role (k depth, stages), measured on MI355X: the inverse
+// apply (one full-occupancy launch) runs 32-deep tiles in 2 stages, the
+// forward's per-block launches (few workgroups each) 16-deep tiles in 3.
+template <class Role> struct StreamCfg { static constexpr int TK = 16, NS = 3; };
+template <> struct StreamCfg<RoleApplyInverse> { static constexpr int TK = 32, NS = 2; };
 
 // Each task's descriptor selects the matrix precision (GemmDesc::fp32).
 template <bool ARF, bool BCF, class Role>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs,
                                                    const GemmTask* __restrict__ tasks) {
-  __shared__ __align__(16) double smem[(ARF && BCF) ? (kStreamSmemBytes / 8 > kSmemDoubles ? kStreamSmemBytes / 8 : kSmemDoubles)
-                                                   : kSmemDoubles];
+  typedef StreamCfg<Role> SC;
+  constexpr int kStream = SC::NS * StreamShape<double, SC::TK>::STAGE / 8;
+  __shared__ __align__(16) double smem[(ARF && BCF) ? (kStream > kSmemDoubles ? kStream : kSmemDoubles) : kSmemDoubles];
   // Workgroups are dispatched round-robin over the 8 XCDs.  Tasks come in
   // descriptor order, the M tiles of one descriptor (which share its B panel)
   // adjacent; runs of 16 consecutive tasks go to workgroups of one XCD, so a
@@ -469,13 +377,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
   }
   const GemmTask t = tasks[ti];
   const GemmDesc d = descs[t.desc];
-  // Column-major A streams through LDS (measured fastest on MI355X for FP32
-  // and for the forward's per-block launches), except the FP64 inverse apply,
-  // a single full-occupancy launch where register-direct A is ahead.
+  // column-major A streams through LDS
   if constexpr (ARF && BCF) {
-    if (d.fp32) gemm_tile_stream<float>(d, t, reinterpret_cast<char*>(smem));
-    else if constexpr (std::is_same<Role, RoleApplyInverse>::value) gemm_tile_cm<double>(d, t, smem);
-    else gemm_tile_stream<double>(d, t, reinterpret_cast<char*>(smem));
+    if (d.fp32) gemm_tile_stream<float, SC::TK, SC::NS>(d, t, reinterpret_cast<char*>(smem));
+    else gemm_tile_stream<double, SC::TK, SC::NS>(d, t, reinterpret_cast<char*>(smem));
   } else {
     if (d.fp32) gemm_tile<ARF, BCF, float>(d, t, smem);
     else gemm_tile<ARF, BCF, double>(d, t, smem);

@@ -445,7 +445,9 @@ void build_plan(Plan& p) {
   while (!fwd_blocks_fit(p, b) && b > 1) b = std::max(1, b * 3 / 4);
   if (p.fp32) {
     // FP32 copies at the same element offsets.  A_m is released; Q_m stays
-    // in FP64 for its alias rows (A_m^top P_m^{-1}) and the forward adjoint
+    // in FP64 (the forward's alias rows A_m^top P_m^{-1} and the forward
+    // adjoint always use it), with an FP32 copy for the coefficient rows
+    // under OSHT_PREC_FP32_FWD
     auto narrow = [](DevBuf& src, DevBuf& dst, bool release) {
       const int64_t n = (int64_t)(src.bytes / sizeof(double));
       dst.alloc(sizeof(float) * std::max<int64_t>(n, 1));
@@ -456,7 +458,7 @@ void build_plan(Plan& p) {
       if (release) src.release();
     };
     narrow(p.d_A, p.d_A32, true);
-    narrow(p.d_Q, p.d_Q32, false);
+    if (p.fp32_fwd) narrow(p.d_Q, p.d_Q32, false);
   }
   if ((p.flags & OSHT_TUNE) && !env) tune_forward_blocks(p);
   OSHT_HIP(hipDeviceSynchronize());

@@ -29,6 +29,10 @@
 #include "xform.hpp"
 
 namespace osht {
+void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, double* f, int64_t B, hipStream_t st);
+}
+
+namespace osht {
 
 namespace {
 
@@ -64,20 +68,24 @@ __global__ __launch_bounds__(256) void block_gather_kernel(Geo g, const Slot* __
 }
 
 // The rows of small rings (k < kthr) alias ~(2L-1)/n_k solved orders each.
-// One workgroup per (slot, row): threads split the columns and, for each
-// column, the alias list into C interleaved chunks whose partial sums are
-// reduced in a fixed order through LDS.
-__global__ __launch_bounds__(256) void wide_gather_kernel(Geo g, const Slot* __restrict__ slots,
-                                                          const int32_t* __restrict__ wide_slot,
-                                                          const int32_t* __restrict__ wide_row, int q1,
-                                                          const double2* __restrict__ H, const double* __restrict__ Y,
-                                                          double2* __restrict__ X) {
-  __shared__ double2 part[256];
+// One workgroup of 1024 threads per (slot, row): threads split the columns
+// and, for each column, the alias list into C interleaved chunks whose
+// partial sums are reduced in a fixed order through LDS.  Each thread keeps
+// four alias loads in flight (an excluded order loads Y[0] instead and is
+// dropped by a select).
+constexpr int kWideThreads = 1024;
+__global__ __launch_bounds__(kWideThreads) void wide_gather_kernel(Geo g, const Slot* __restrict__ slots,
+                                                                   const int32_t* __restrict__ wide_slot,
+                                                                   const int32_t* __restrict__ wide_row, int q1,
+                                                                   const double2* __restrict__ H,
+                                                                   const double* __restrict__ Y,
+                                                                   double2* __restrict__ X) {
+  __shared__ double2 part[kWideThreads];
   const int slot = wide_slot[blockIdx.x], r = wide_row[blockIdx.x];
   const Slot sl = slots[slot];
   const int nc = g.ncols >> 1;
-  const int cw = nc < 256 ? nc : 256;  // columns in flight
-  const int C = 256 / cw;              // alias chunks per column
+  const int cw = nc < kWideThreads ? nc : kWideThreads;  // columns in flight
+  const int C = kWideThreads / cw;                        // alias chunks per column
   const int ci = threadIdx.x % cw, chunk = threadIdx.x / cw;
   for (int cc0 = 0; cc0 < nc; cc0 += cw) {
     const int cc = cc0 + ci;
@@ -91,7 +99,24 @@ __global__ __launch_bounds__(256) void wide_gather_kernel(Geo g, const Slot* __r
       const int n = 2 * k + 1;
       bin = pmod(m, n);
       const int start = bin - ((bin + g.L - 1) / n) * n;
-      for (int mp = start + chunk * n; mp <= g.L - 1; mp += C * n) {
+      const int step = C * n;
+      int mp = start + chunk * n;
+      for (; mp + 3 * step <= g.L - 1; mp += 4 * step) {
+        double2 a[4];
+        bool use[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int q = mp + t * step, aq = q < 0 ? -q : q;
+          use[t] = q != m && aq >= q1;  // then |q| > k and the alias row exists
+          a[t] = *reinterpret_cast<const double2*>(Y + (use[t] ? alias_index(g, slots, q, k, b, 0) : 0));
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          acc.x += use[t] ? a[t].x : 0.0;
+          acc.y += use[t] ? a[t].y : 0.0;
+        }
+      }
+      for (; mp <= g.L - 1; mp += step) {
         const int amp = mp < 0 ? -mp : mp;
         if (mp == m || amp < q1) continue;
         const double2 a = *reinterpret_cast<const double2*>(Y + alias_index(g, slots, mp, k, b, 0));
@@ -178,7 +203,18 @@ __global__ __launch_bounds__(512) void delta_solve_kernel(Geo g, int u0, int nu,
       if (e < items) {
         ul = a + e / cpw;
         jj = e % cpw;
-        for (int w = wp[ul] + lg; w < wp[ul + 1]; w += G) part += wv[w] * dl[wc[w] * cpw + jj];
+        int w = wp[ul] + lg;
+        const int we = wp[ul + 1];
+        // four W entries per lane in flight before their delta reads
+        for (; w + 3 * G < we; w += 4 * G) {
+          const double v0 = wv[w], v1 = wv[w + G], v2 = wv[w + 2 * G], v3 = wv[w + 3 * G];
+          const int c0 = wc[w], c1 = wc[w + G], c2 = wc[w + 2 * G], c3 = wc[w + 3 * G];
+          part += v0 * dl[c0 * cpw + jj];
+          part += v1 * dl[c1 * cpw + jj];
+          part += v2 * dl[c2 * cpw + jj];
+          part += v3 * dl[c3 * cpw + jj];
+        }
+        for (; w < we; w += G) part += wv[w] * dl[wc[w] * cpw + jj];
       }
 #pragma unroll
       for (int off = 1; off < G; off <<= 1) part += __shfl_xor(part, off, G);
@@ -192,6 +228,126 @@ __global__ __launch_bounds__(512) void delta_solve_kernel(Geo g, int u0, int nu,
       const int u = u0 + ul;
       D[((int64_t)unk_slot[u] * bD + unk_r[u]) * g.ncols + order_col(g, unk_m[u], j)] = dl[e];
     }
+  }
+}
+
+// ---------------------------------------------------------------- adjoint
+// The adjoint of the blocked forward runs the blocks in ascending order.
+// For block [q0, q1) with y_m = Q_m (h_m - E delta), delta = (I + W)^{-1} A Q h:
+//   z = Q^T ybar;  (I + W^T) eps = z restricted to the unknowns;
+//   hbar = z - Q^T A^T eps;  Hbar_k[m mod n_k] = hbar_m[k] (m owns that bin).
+// ybar_m holds flm_bar on its coefficient rows and, on an alias row k < |m|,
+// -Hbar_k[m mod n_k] when the owner of that bin (the order congruent to m in
+// [-k, k]) lies below the block; owners inside the block are covered by eps.
+
+// ybar for the block's slots: X[slot][i][col], i < K + |m|.
+__global__ __launch_bounds__(256) void fadj_block_gather_kernel(Geo g, const Slot* __restrict__ slots,
+                                                                const int32_t* __restrict__ slot_list, int q0,
+                                                                const double* __restrict__ flmbar,
+                                                                const double* __restrict__ H, double* __restrict__ X) {
+  const int slot = slot_list[blockIdx.y];
+  const Slot sl = slots[slot];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = e / g.ncols, col = e % g.ncols;
+  int sgn, b, part, m;
+  decode_col(g, sl, col, sgn, b, part, m);
+  const int am = m < 0 ? -m : m;
+  if (i >= sl.K + am) return;
+  double v = 0.0;
+  if (i < sl.K) {
+    const int l = sl.l0 + i;
+    v = flmbar[((int64_t)b * g.L * g.L + (int64_t)l * l + l + m) * 2 + part];
+    if (g.s == 0 && sgn && (am & 1)) v = -v;
+  } else {
+    const int k = i - sl.K, n = 2 * k + 1;
+    const int owner = pmod(m + k, n) - k;  // the order congruent to m in [-k, k]
+    if ((owner < 0 ? -owner : owner) < q0) v = -H[(((int64_t)k * k + pmod(m, n)) * g.B + b) * 2 + part];
+  }
+  X[((int64_t)slot * g.L + i) * g.ncols + col] = v;
+}
+
+// Hbar_k[m mod n_k] = Z[slot][k - |m|][col] for the block's slots.
+__global__ __launch_bounds__(256) void fadj_block_scatter_kernel(Geo g, const Slot* __restrict__ slots,
+                                                                 const int32_t* __restrict__ slot_list,
+                                                                 const double* __restrict__ Y, double* __restrict__ H) {
+  const int slot = slot_list[blockIdx.y];
+  const Slot sl = slots[slot];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = e / g.ncols, col = e % g.ncols;
+  if (r >= sl.R) return;
+  int sgn, b, part, m;
+  decode_col(g, sl, col, sgn, b, part, m);
+  if (g.s == 0 && sgn && sl.m == 0) return;  // -0 duplicates +0
+  const int am = m < 0 ? -m : m;
+  const int k = am + r, n = 2 * k + 1;
+  H[(((int64_t)k * k + pmod(m, n)) * g.B + b) * 2 + part] = Y[((int64_t)slot * g.L + r) * g.ncols + col];
+}
+
+// (I + W^T) eps = zeta, ascending levels, in LDS; zeta_u = Z of the owner of
+// u at its ring.  Then E[source slot][k - q0][col] = eps_u for every alias
+// source of u = (m, k) (each (source, k) pair has exactly one owner u).
+__global__ __launch_bounds__(512) void eps_solve_kernel(Geo g, int u0, int nu, int nlev, int cpw, int q0,
+                                                        const int32_t* __restrict__ lev_ptr,
+                                                        const int32_t* __restrict__ unk_slot,
+                                                        const int32_t* __restrict__ unk_r,
+                                                        const int32_t* __restrict__ unk_m,
+                                                        const int32_t* __restrict__ src_ptr,
+                                                        const int32_t* __restrict__ src_slot,
+                                                        const int32_t* __restrict__ src_m,
+                                                        const int64_t* __restrict__ wt_ptr,
+                                                        const int32_t* __restrict__ wt_row,
+                                                        const double* __restrict__ wt_val, const double* __restrict__ Y,
+                                                        double* __restrict__ D, int bD) {
+  extern __shared__ double lds[];
+  const int64_t wbase = wt_ptr[u0];
+  const int nw = (int)(wt_ptr[u0 + nu] - wbase);
+  double* el = lds;                                    // nu * cpw
+  double* wv = lds + (size_t)nu * cpw;                 // nw
+  int32_t* wr = reinterpret_cast<int32_t*>(wv + nw);   // nw
+  int32_t* wp = wr + nw;                               // nu + 1
+  const int j0 = blockIdx.x * cpw;
+  const int J = 2 * g.B;
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) {
+    wv[i] = wt_val[wbase + i];
+    wr[i] = wt_row[wbase + i];
+  }
+  for (int i = threadIdx.x; i <= nu; i += blockDim.x) wp[i] = (int32_t)(wt_ptr[u0 + i] - wbase);
+  for (int e = threadIdx.x; e < nu * cpw; e += blockDim.x) {
+    const int ul = e / cpw, jj = e - ul * cpw, j = j0 + jj;
+    const int u = u0 + ul;
+    el[e] = (j < J) ? Y[((int64_t)unk_slot[u] * g.L + unk_r[u]) * g.ncols + order_col(g, unk_m[u], j)] : 0.0;
+  }
+  __syncthreads();
+  // lev_ptr lists the block's levels in descending |m|; W^T couples each
+  // unknown to unknowns of lower levels, so walk the list backwards
+  constexpr int G = 8;
+  const int grp = threadIdx.x / G, lg = threadIdx.x % G, ngrp = blockDim.x / G;
+  for (int lv = nlev - 1; lv >= 0; --lv) {
+    const int a = lev_ptr[lv] - u0, b = lev_ptr[lv + 1] - u0;
+    const int items = (b - a) * cpw;
+    for (int e0 = 0; e0 < items; e0 += ngrp) {
+      const int e = e0 + grp;
+      double part = 0.0;
+      int ul = 0, jj = 0;
+      if (e < items) {
+        ul = a + e / cpw;
+        jj = e % cpw;
+        for (int w = wp[ul] + lg; w < wp[ul + 1]; w += G) part += wv[w] * el[wr[w] * cpw + jj];
+      }
+#pragma unroll
+      for (int off = 1; off < G; off <<= 1) part += __shfl_xor(part, off, G);
+      if (e < items && lg == 0) el[ul * cpw + jj] -= part;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nu * cpw; e += blockDim.x) {
+    const int ul = e / cpw, jj = e - ul * cpw, j = j0 + jj;
+    if (j >= J) continue;
+    const int u = u0 + ul;
+    const int am = unk_m[u] < 0 ? -unk_m[u] : unk_m[u];
+    const int k = unk_r[u] + am;
+    for (int s = src_ptr[u]; s < src_ptr[u + 1]; ++s)
+      D[((int64_t)src_slot[s] * bD + (k - q0)) * g.ncols + order_col(g, src_m[s], j)] = el[e];
   }
 }
 
@@ -226,6 +382,7 @@ void build_fwd_blocks(Plan& p, int b) {
   fb.lev_blk_ptr.push_back(0);
   fb.src_ptr.push_back(0);
   fb.w_ptr.push_back(0);
+  fb.wt_ptr.push_back(0);
   fb.wide_ptr.push_back(0);
   // rings with more than ~64 aliased orders per bin: n_k * 64 < 2L - 1
   fb.kthr = 0;
@@ -293,6 +450,24 @@ void build_fwd_blocks(Plan& p, int b) {
     }
     fb.unk_ptr.push_back((int32_t)fb.unk_m.size());
     fb.max_unk = std::max(fb.max_unk, (int)unks.size());
+    // W^T for the forward adjoint: column u' of W as a list of (u, value),
+    // u in the order of the rows of W
+    {
+      const int nu = (int)unks.size();
+      std::vector<std::vector<std::pair<int32_t, int64_t>>> col(nu);
+      const int64_t wb = fb.w_ptr[u0];
+      for (int ul = 0; ul < nu; ++ul)
+        for (int64_t w = fb.w_ptr[u0 + ul]; w < fb.w_ptr[u0 + ul + 1]; ++w)
+          col[fb.w_col[w]].push_back({ul, fb.w_idx[w]});
+      (void)wb;
+      for (int c = 0; c < nu; ++c) {
+        for (const auto& e : col[c]) {
+          fb.wt_row.push_back(e.first);
+          fb.wt_idx.push_back(e.second);
+        }
+        fb.wt_ptr.push_back((int64_t)fb.wt_row.size());
+      }
+    }
     // rows of small rings gathered by the wide kernel
     for (int i = fb.slot_ptr[fb.slot_ptr.size() - 2]; i < fb.slot_ptr.back(); ++i) {
       const int sp = fb.slot_list[i];
@@ -317,6 +492,8 @@ void build_fwd_blocks(Plan& p, int b) {
   put_vec(fb.d_w_col, fb.w_col);
   put_vec(fb.d_wide_slot, fb.wide_slot);
   put_vec(fb.d_wide_row, fb.wide_row);
+  put_vec(fb.d_wt_ptr, fb.wt_ptr);
+  put_vec(fb.d_wt_row, fb.wt_row);
   const int64_t nw = (int64_t)fb.w_idx.size();
   fb.d_w_val.alloc(std::max<int64_t>(nw, 1) * sizeof(double));
   if (nw > 0) {
@@ -329,6 +506,18 @@ void build_fwd_blocks(Plan& p, int b) {
   }
   fb.w_idx.clear();
   fb.w_idx.shrink_to_fit();
+  const int64_t nwt = (int64_t)fb.wt_idx.size();
+  fb.d_wt_val.alloc(std::max<int64_t>(nwt, 1) * sizeof(double));
+  if (nwt > 0) {
+    DevBuf d_idx;
+    put_vec(d_idx, fb.wt_idx);
+    hipLaunchKernelGGL(gather_values_kernel, dim3((unsigned)ceil_div(nwt, 256)), dim3(256), 0, 0,
+                       p.d_Q.as<double>(), d_idx.as<int64_t>(), fb.d_wt_val.as<double>(), nwt);
+    OSHT_HIP(hipGetLastError());
+    OSHT_HIP(hipDeviceSynchronize());
+  }
+  fb.wt_idx.clear();
+  fb.wt_idx.shrink_to_fit();
   // LDS need of the delta solve per block: delta for cpw columns + W
   fb.max_w = 0;
   for (size_t blk = 0; blk + 1 < fb.unk_ptr.size(); ++blk) {
@@ -365,7 +554,7 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
       OSHT_HIP(hipGetLastError());
       const int nwide = fb.wide_ptr[blk + 1] - fb.wide_ptr[blk];
       if (nwide > 0) {
-        hipLaunchKernelGGL(wide_gather_kernel, dim3((unsigned)nwide), dim3(256), 0, st, g, p.d_slots.as<Slot>(),
+        hipLaunchKernelGGL(wide_gather_kernel, dim3((unsigned)nwide), dim3(kWideThreads), 0, st, g, p.d_slots.as<Slot>(),
                            fb.d_wide_slot.as<int32_t>() + fb.wide_ptr[blk], fb.d_wide_row.as<int32_t>() + fb.wide_ptr[blk],
                            fb.q1[blk], reinterpret_cast<const double2*>(p.w_H.as<double>()), p.w_Y.as<double>(),
                            reinterpret_cast<double2*>(p.w_X.as<double>()));
@@ -418,7 +607,7 @@ std::string tune_path(const Plan& p) {
   for (char& c : arch)
     if (c == ':' || c == '/' || c == ' ') c = '_';
   return p.cache_dir + "/tune_fwd_" + arch + "_L" + std::to_string(p.L) + "_s" + std::to_string(p.spin) + "_p" +
-         std::to_string(p.fp32 ? 1 : 0) + ".txt";
+         std::to_string(p.fp32_fwd ? 2 : p.fp32 ? 1 : 0) + ".txt";
 }
 
 }  // namespace
@@ -488,6 +677,51 @@ void tune_forward_blocks(Plan& p) {
   p.w_Y.release();
   p.w_H.release();
   p.w_D.release();
+}
+
+void run_forward_adjoint_blocked(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st) {
+  ensure_workspace(p, B);
+  const Geo g = geo(p, B);
+  const FwdBlocks& fb = p.fb;
+  const int bD = std::max(fb.b, 1);
+  const int64_t nD = (int64_t)p.nslots * bD * g.ncols;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nD, 256), 4096)), dim3(256), 0, st,
+                     p.w_D.as<double>(), nD);
+  OSHT_HIP(hipGetLastError());
+  OSHT_HIP(hipFuncSetAttribute((const void*)eps_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                fb.lds_limit));
+  const int nblk = (int)fb.q0.size();
+  const GemmTask* at = p.d_atask.as<GemmTask>();
+  double* H = p.w_H.as<double>();
+  for (int blk = nblk - 1; blk >= 0; --blk) {  // ascending orders
+    const int ns = fb.slot_ptr[blk + 1] - fb.slot_ptr[blk];
+    const int32_t* sl = fb.d_slot_list.as<int32_t>() + fb.slot_ptr[blk];
+    const dim3 grid((unsigned)ceil_div((int64_t)p.L * g.ncols, 256), ns);
+    hipLaunchKernelGGL(fadj_block_gather_kernel, grid, dim3(256), 0, st, g, p.d_slots.as<Slot>(), sl, fb.q0[blk], flmbar,
+                       H, p.w_X.as<double>());
+    OSHT_HIP(hipGetLastError());
+    const int* tp = &p.h_atask_ptr[2 * blk];
+    gemm_tasks_launch(p, at + tp[0], tp[1] - tp[0], GemmRole::Adjoint, "apply_forward_adjoint", st);
+    const int u0 = fb.unk_ptr[blk], nu = fb.unk_ptr[blk + 1] - u0;
+    if (nu > 0) {
+      const int lv0 = fb.lev_blk_ptr[blk], lv1 = fb.lev_blk_ptr[blk + 1];
+      const int64_t nw = fb.wt_ptr[u0 + nu] - fb.wt_ptr[u0];
+      const int cpw = fb.cpw;
+      const size_t lds = sizeof(double) * ((size_t)nu * cpw + nw) + sizeof(int32_t) * (nw + nu + 1);
+      hipLaunchKernelGGL(eps_solve_kernel, dim3((unsigned)ceil_div(2 * B, cpw)), dim3(512), lds, st, g, u0, nu,
+                         lv1 - lv0 - 1, cpw, fb.q0[blk], fb.d_lev_ptr.as<int32_t>() + lv0, fb.d_unk_slot.as<int32_t>(),
+                         fb.d_unk_r.as<int32_t>(), fb.d_unk_m.as<int32_t>(), fb.d_src_ptr.as<int32_t>(),
+                         fb.d_src_slot.as<int32_t>(), fb.d_src_m.as<int32_t>(), fb.d_wt_ptr.as<int64_t>(),
+                         fb.d_wt_row.as<int32_t>(), fb.d_wt_val.as<double>(), p.w_Y.as<double>(), p.w_D.as<double>(),
+                         bD);
+      OSHT_HIP(hipGetLastError());
+      gemm_tasks_launch(p, at + tp[1], tp[2] - tp[1], GemmRole::Adjoint, "apply_forward_adjoint_correction", st);
+    }
+    hipLaunchKernelGGL(fadj_block_scatter_kernel, dim3((unsigned)ceil_div((int64_t)p.L * g.ncols, 256), ns), dim3(256),
+                       0, st, g, p.d_slots.as<Slot>(), sl, p.w_Y.as<double>(), H);
+    OSHT_HIP(hipGetLastError());
+  }
+  launch_ring_synthesis(p, H, 1, fbar, B, st);
 }
 
 }  // namespace osht

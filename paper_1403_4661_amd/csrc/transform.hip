@@ -33,7 +33,8 @@ void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, doub
 namespace {
 
 // Coefficients (l-major, map-major) <-> slot layout, through an LDS tile of
-// 64 consecutive orders x 16 maps per step: one workgroup per degree l.
+// 64 consecutive orders x 16 maps per step: one workgroup per (degree l,
+// chunk of 64 orders), so that the long rows of high degrees are spread.
 // to_slots: X[slot(m)][l - l0(m)][col(m, b)] = sign(m) * flm[b][l^2 + l + m]
 // else:     flm[b][l^2 + l + m] = sign(m) * Y[slot(m)][l - l0(m)][col(m, b)],
 //           zero when l < l0(m) (spin: degrees below |s|).
@@ -42,11 +43,13 @@ template <bool TO_SLOTS>
 __global__ __launch_bounds__(256) void coef_transpose_kernel(Geo g, const double2* __restrict__ src,
                                                              double2* __restrict__ dst) {
   __shared__ double2 tile[16][65];
-  const int l = blockIdx.x;
+  const int l = blockIdx.y;
   const int nc = g.ncols >> 1;
   const int as = g.s < 0 ? -g.s : g.s;
   const int64_t LL = (int64_t)g.L * g.L;
-  for (int m0 = -l; m0 <= l; m0 += 64) {
+  {
+    const int m0 = -l + 64 * (int)blockIdx.x;
+    if (m0 > l) return;  // uniform over the workgroup
     const int nm = min(64, l - m0 + 1);
     for (int b0 = 0; b0 < g.B; b0 += 16) {
       const int nb = min(16, g.B - b0);
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(256) void fadj_scatter_kernel(Geo g, const Slot* __
 const char* const kApplyName[kNumDir] = {"apply_inverse",           "apply_forward",
                                          "apply_inverse_adjoint",   "apply_forward_adjoint",
                                          "apply_forward_correction", "apply_forward",
-                                         "apply_forward_correction"};
+                                         "apply_forward_correction", "apply_forward_adjoint_correction"};
 
 // Workspace and GEMM descriptors for batch B (rebuilt when B or the buffers
 // change).  Descriptor d = dir * nslots + slot; tasks of all directions are
@@ -202,20 +205,23 @@ void ensure_workspace(Plan& p, int64_t B) {
   double* Y = p.w_Y.as<double>();
   double* D = p.w_D.as<double>();
   // Matrix element offsets are the same in the FP64 and FP32 copies.  FP32
-  // plans apply A_m (inverse and its adjoint) and the coefficient rows of
-  // Q_m (P_m^{-1}) in FP32; the alias rows of Q_m (A_m^top P_m^{-1}), which
-  // feed the descending-order chain, and the forward adjoint stay FP64.
+  // plans apply A_m (inverse and its adjoint) in FP32; OSHT_PREC_FP32_FWD
+  // also the coefficient rows of Q_m (P_m^{-1}).  The alias rows of Q_m
+  // (A_m^top P_m^{-1}), which feed the descending-order chain, and the
+  // forward adjoint stay FP64.
   const double* A64 = p.d_A.as<double>();
   const double* Q64 = p.d_Q.as<double>();
   const float* A32 = p.d_A32.as<float>();
   const float* Q32 = p.d_Q32.as<float>();
-  const bool f32 = p.fp32;
+  const bool f32 = p.fp32;          // A_m in FP32
+  const bool f32q = p.fp32_fwd;     // coefficient rows of Q_m in FP32
   const int bD = std::max(p.fb.b, 1);
-  std::vector<int32_t> wcorr(p.nslots, 0);  // correction width per slot
+  std::vector<int32_t> wcorr(p.nslots, 0), q0of(p.nslots, 0);  // correction width, block start per slot
   for (size_t blk = 0; blk + 1 < p.fb.slot_ptr.size(); ++blk)
     for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) {
       const int slot = p.fb.slot_list[i];
       wcorr[slot] = p.fb.q1[blk] - std::abs(p.slots[slot].m);
+      q0of[slot] = p.fb.q0[blk];
     }
   for (int dir = 0; dir < kNumDir; ++dir) {
     for (int i = 0; i < p.nslots; ++i) {
@@ -235,14 +241,20 @@ void ensure_workspace(Plan& p, int64_t B) {
       if (dir == kInv) { setA(f32, true, sl.offA); d.sAr = 1; d.sAc = sl.ldA; d.M = p.L; d.K = sl.K; }
       if (dir == kIadj) { setA(f32, true, sl.offA); d.sAr = sl.ldA; d.sAc = 1; d.M = sl.K; d.K = p.L; }
       if (dir == kFadj) { setA(false, false, sl.offQ); d.sAr = sl.ldQ; d.sAc = 1; d.M = sl.R; d.K = sl.K + am; }
+      if (dir == kFadjCorr) {  // Z -= Q^T[:, K + q0 .. K + |m|) E, E rows k - q0
+        setA(false, false, sl.offQ + sl.K + q0of[i]);
+        d.sAr = sl.ldQ; d.sAc = 1; d.M = sl.R; d.K = std::max(0, am - q0of[i]);
+        d.B = D + (int64_t)i * bD * ncols;
+        d.alpha = -1.0; d.beta = 1.0;
+      }
       if (dir == kFwd || dir == kCorr || dir == kFwdAlias || dir == kCorrAlias) {
         // rows [0, K) (coefficients) in the main descriptor, rows [K, K+|m|)
         // (aliases) in the alias one when the plan is FP32
         // descriptors keep column-base pointers and select rows by [m_lo, M)
         const bool alias = dir == kFwdAlias || dir == kCorrAlias;
         const int r0 = alias ? sl.K : 0;
-        const int r1 = f32 ? (alias ? sl.K + am : sl.K) : (alias ? 0 : sl.K + am);
-        setA(f32 && !alias, false, sl.offQ);
+        const int r1 = f32q ? (alias ? sl.K + am : sl.K) : (alias ? 0 : sl.K + am);
+        setA(f32q && !alias, false, sl.offQ);
         d.sAr = 1; d.sAc = sl.ldQ;
         d.m_lo = r1 > r0 ? r0 : 0;
         d.M = r1 > r0 ? r1 : 0;
@@ -281,6 +293,26 @@ void ensure_workspace(Plan& p, int64_t B) {
   }
   p.h_btask_ptr.push_back((int32_t)bt.size());
   upload(p.d_btask, bt);
+  // per-block task lists of the blocked forward adjoint: [Q^T apply, correction]
+  std::vector<GemmTask> at;
+  p.h_atask_ptr.clear();
+  auto emit_to = [&](std::vector<GemmTask>& v, int d) {
+    const GemmDesc& g = p.h_gdesc[d];
+    if (g.K <= 0 || g.M <= g.m_lo) return;
+    for (int a = g.m_lo / 64; a < (int)ceil_div(g.M, 64); ++a)
+      for (int c = 0; c < (int)ceil_div(g.N, 64); ++c) v.push_back(GemmTask{d, a, c, 0});
+  };
+  for (int blk = 0; blk < nblk; ++blk) {
+    const bool has_unk = p.fb.unk_ptr[blk + 1] > p.fb.unk_ptr[blk];
+    p.h_atask_ptr.push_back((int32_t)at.size());
+    for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) emit_to(at, kFadj * p.nslots + p.fb.slot_list[i]);
+    p.h_atask_ptr.push_back((int32_t)at.size());
+    if (has_unk)
+      for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i)
+        emit_to(at, kFadjCorr * p.nslots + p.fb.slot_list[i]);
+  }
+  p.h_atask_ptr.push_back((int32_t)at.size());
+  upload(p.d_atask, at);
   p.ws_batch = B;
 }
 
@@ -288,14 +320,14 @@ void prepare_transforms(Plan& p, int64_t B) { ensure_workspace(p, B); }
 
 void launch_fwd_scatter(const Plan& p, const double* Y, double* flm, int64_t B, hipStream_t st) {
   const Geo g = geo(p, B);
-  hipLaunchKernelGGL(coef_transpose_kernel<false>, dim3(p.L), dim3(256), 0, st, g,
+  hipLaunchKernelGGL(coef_transpose_kernel<false>, dim3((unsigned)ceil_div(2 * p.L - 1, 64), p.L), dim3(256), 0, st, g,
                      reinterpret_cast<const double2*>(Y), reinterpret_cast<double2*>(flm));
   OSHT_HIP(hipGetLastError());
 }
 
 void launch_coef_to_slots(const Plan& p, const double* flm, double* X, int64_t B, hipStream_t st) {
   const Geo g = geo(p, B);
-  hipLaunchKernelGGL(coef_transpose_kernel<true>, dim3(p.L), dim3(256), 0, st, g,
+  hipLaunchKernelGGL(coef_transpose_kernel<true>, dim3((unsigned)ceil_div(2 * p.L - 1, 64), p.L), dim3(256), 0, st, g,
                      reinterpret_cast<const double2*>(flm), reinterpret_cast<double2*>(X));
   OSHT_HIP(hipGetLastError());
 }
@@ -407,6 +439,10 @@ void run_inverse_adjoint(Plan& p, const double* fbar, double* flmbar, int64_t B,
 }
 
 void run_forward_adjoint(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st) {
+  if (p.fb.b > 1) {
+    run_forward_adjoint_blocked(p, flmbar, fbar, B, st);
+    return;
+  }
   ensure_workspace(p, B);
   const Geo g = geo(p, B);
   const dim3 blk(256);

@@ -51,7 +51,8 @@ __device__ __forceinline__ int64_t alias_index(const Geo& g, const Slot* __restr
 
 // GEMM directions; kFwdAlias / kCorrAlias carry the alias rows of Q_m
 // separately in FP32 plans (empty otherwise).
-enum { kInv = 0, kFwd = 1, kIadj = 2, kFadj = 3, kCorr = 4, kFwdAlias = 5, kCorrAlias = 6, kNumDir = 7 };
+// kFadjCorr: the blocked forward adjoint's correction Z_m -= Q_m^T[:, alias rows of the block] E_m.
+enum { kInv = 0, kFwd = 1, kIadj = 2, kFadj = 3, kCorr = 4, kFwdAlias = 5, kCorrAlias = 6, kFadjCorr = 7, kNumDir = 8 };
 
 void ensure_workspace(Plan& p, int64_t B);
 void launch_fwd_scatter(const Plan& p, const double* Y, double* flm, int64_t B, hipStream_t st);

@@ -1,7 +1,7 @@
 """Batch scheduler (osht_batch_run): 64 maps of uneven band-limit and spin,
 L in {64, 128, 256, 512} and s in {0, 2, -2} drawn from seed 2, flm ~ N(0,1)
-zeroed for l < |s|, on FP32 plans (FP32 matrix-core applies, FP64 alias
-rows), run as one unit: one job per (L, s) group with its maps stored
+zeroed for l < |s|, on FP32 plans (OSHT_PREC_FP32_FWD: FP32 matrix-core
+applies of A_m and P_m^{-1}, FP64 alias rows), run as one unit: one job per (L, s) group with its maps stored
 contiguously, captured into a HIP graph and replayed.
 
 Checks per map: the inverse against the oracle on sampled rings (first,
@@ -34,7 +34,7 @@ def test_uneven_batch_graph_matches_oracle_and_direct_calls():
 
     groups, maps = _groups()
     keys = sorted(groups)
-    plans = {k: Plan(k[0], k[1], precision="fp32") for k in keys}
+    plans = {k: Plan(k[0], k[1], precision="fp32-fwd") for k in keys}
     flm = {k: to_dev(np.stack([maps[i] for i in groups[k]])) for k in keys}
     f = {k: torch.empty_like(flm[k]) for k in keys}
     g = BatchGraph()
@@ -78,7 +78,7 @@ def test_uneven_batch_forward_spin0():
 
     groups, maps = _groups()
     keys = sorted(k for k in groups if k[1] == 0)
-    plans = {k: Plan(k[0], 0, precision="fp32") for k in keys}
+    plans = {k: Plan(k[0], 0, precision="fp32-fwd") for k in keys}
     flm = {k: np.stack([maps[i] for i in groups[k]]) for k in keys}
     f = {k: to_dev(sht.inverse(oracle_plan(k[0]), flm[k])) for k in keys}
     back = {k: torch.empty_like(f[k]) for k in keys}

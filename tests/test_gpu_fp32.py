@@ -1,11 +1,13 @@
-"""GPU parity of FP32 plans (OSHT_PREC_FP32) against the FP64 oracle.
+"""GPU parity of the FP32 precision modes against the FP64 oracle.
 
-FP32 plans apply A_m and the coefficient rows P_m^{-1} of Q_m with FP32
-matrices on FP32 matrix cores (16-term FP32 slices summed in FP64); the alias
-rows of Q_m, which feed the descending-order chain of Procedure 1, the ring
-DFTs and all buffers stay FP64.  Tolerance: 1e-6 max relative error, the bar
-for the mixed-precision path (an FP32 rounding of 6e-8 per matrix entry and
-per right-hand-side entry, amplified by the conditioning of P_m)."""
+OSHT_PREC_FP32 ("fp32") applies A_m (inverse and its adjoint) with FP32
+matrices on FP32 matrix cores (16-term FP32 slices summed in FP64);
+OSHT_PREC_FP32_FWD ("fp32-fwd") also the forward's coefficient rows
+P_m^{-1}.  The alias rows of Q_m, which feed the descending-order chain of
+Procedure 1, the ring DFTs and all buffers stay FP64.  Tolerance: 1e-6 max
+relative error, the bar for the mixed-precision path (an FP32 rounding of
+6e-8 per matrix entry and per right-hand-side entry, amplified by the
+conditioning of P_m)."""
 
 import numpy as np
 import pytest
@@ -19,11 +21,11 @@ TOL = 1e-6
 _plans = {}
 
 
-def plan32(L, s=0):
+def plan32(L, s=0, precision="fp32"):
     from paper_1403_4661_amd import Plan
-    if (L, s) not in _plans:
-        _plans[(L, s)] = Plan(L, s, precision="fp32")
-    return _plans[(L, s)]
+    if (L, s, precision) not in _plans:
+        _plans[(L, s, precision)] = Plan(L, s, precision=precision)
+    return _plans[(L, s, precision)]
 
 
 _oplans = {}
@@ -37,8 +39,9 @@ def oplan(L, s=0):
 
 def test_fp32_plan_memory_and_flags():
     from paper_1403_4661_amd import Plan
-    p64, p32 = Plan(64), plan32(64)
-    assert p32.info()["flags"] & 0xF == 1
+    p64, p32, p32f = Plan(64), plan32(64), plan32(64, 0, "fp32-fwd")
+    assert p32.info()["flags"] & 0xF == 1 and p32f.info()["flags"] & 0xF == 2
+    assert p32.info()["device_bytes"] < p64.info()["device_bytes"]
     # A_m moves to FP32; Q_m is held in FP32 and (for its alias rows) FP64
     assert p32.info()["device_bytes"] <= p64.info()["device_bytes"]
 
@@ -52,13 +55,14 @@ def test_fp32_inverse(L, B, s, weighted, seed):
     assert relmax(got, sht.inverse(oplan(L, s), flm)) < TOL
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp32-fwd"])
 @pytest.mark.parametrize("L,B,weighted,seed", [(33, 3, False, 3), (100, 17, True, 5), (256, 2, True, 1)])
-def test_fp32_forward(L, B, weighted, seed):
+def test_fp32_forward(L, B, weighted, seed, precision):
     from oracle import sht
     op = oplan(L)
     flm = inputs.coeffs(L, B, seed=seed, weighted=weighted)
     f = sht.inverse(op, flm)
-    got = to_host(plan32(L).forward(to_dev(f)))
+    got = to_host(plan32(L, 0, precision).forward(to_dev(f)))
     assert relmax(got, sht.forward(op, f)) < TOL
     assert relmax(got, flm) < TOL
 
@@ -80,7 +84,7 @@ def test_fp32_forward_block_sizes(L, b, monkeypatch):
     from oracle import sht
     from paper_1403_4661_amd import Plan
     monkeypatch.setenv("OSHT_FWD_BLOCK", str(b))
-    p = Plan(L, 0, precision="fp32")
+    p = Plan(L, 0, precision="fp32-fwd")
     flm = inputs.coeffs(L, 2, seed=L + b)
     f = sht.inverse(oplan(L), flm)
     got = to_host(p.forward(to_dev(f)))

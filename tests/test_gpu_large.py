@@ -9,7 +9,8 @@ the checks are properties that hold at any size:
     rounding as |m| falls: on MI355X it measures ~1e-15 for |m| >= 1024,
     3e-13 for 512 <= |m| < 1024, 5e-11 for 256 <= |m| < 512 and up to
     6e-5 for |m| < 256 (the FP64 oracle shows the same growth);
-  * the FP32 plan agrees with the FP64 plan to 1e-6 in both directions."""
+  * the FP32 plan (OSHT_PREC_FP32_FWD) agrees with the FP64 plan to 1e-6 in
+    both directions."""
 
 import numpy as np
 import pytest
@@ -59,7 +60,7 @@ def test_L2048_fp64_pole_and_round_trip():
 
 
 def test_L2048_fp32_matches_fp64():
-    p32 = _plan("fp32")
+    p32 = _plan("fp32-fwd")
     if "f64" not in _cache:
         pytest.skip("needs the FP64 results of the previous test")
     f64, back64 = _cache["f64"]

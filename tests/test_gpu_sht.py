@@ -175,8 +175,12 @@ def test_forward_block_sizes(L, s, b, monkeypatch):
     f = sht.inverse(oplan(L, s), flm)
     ref = sht.forward(oplan(L, s), f)
     got = to_host(p.forward(to_dev(f)))
-    tol = 1e-11 if s == 0 else 1e-8  # spin: alias-chain error growth, see the design doc
+    tol = 1e-11 if s == 0 else 1e-8  # spin: alias-chain error growth (the method's, not the kernels')
     assert relmax(got, ref) < tol
+    # the forward adjoint runs the same blocks in ascending order
+    y = inputs.coeffs(L, 2, seed=L + b + 1, spin=s)
+    fa = to_host(p.forward_adjoint(to_dev(y)))
+    assert relmax(fa, sht.forward_adjoint(oplan(L, s), y)) < (1e-10 if s == 0 else 1e-7)
 
 
 def test_autotuned_plan_matches_oracle_and_caches_choice(tmp_path):
