@@ -149,6 +149,12 @@ struct FwdBlocks {
   int max_unk = 0;
   int64_t max_w = 0;                           // max W entries in one block
   int cpw = 1;                                 // delta-solve columns per workgroup
+  // (I + W)^{-1} of every block, column-major with leading dimension
+  // minv_ld[blk], at element offset minv_off[blk] of d_minv; the forward
+  // then takes delta = (I + W)^{-1} beta as one matrix product per block
+  bool dense = true;
+  std::vector<int64_t> minv_off;
+  std::vector<int32_t> minv_ld;
   int lds_limit = 160 * 1024;
   void clear_host() {
     for (auto* v : {&q0, &q1, &slot_ptr, &slot_list, &unk_ptr, &lev_blk_ptr, &lev_ptr, &unk_slot, &unk_r, &unk_m,
@@ -161,7 +167,7 @@ struct FwdBlocks {
     max_unk = 0;
   }
   DevBuf d_slot_list, d_lev_ptr, d_unk_slot, d_unk_r, d_unk_m, d_src_ptr, d_src_slot, d_src_row, d_src_m,
-      d_w_ptr, d_w_col, d_w_val, d_wide_slot, d_wide_row, d_wt_ptr, d_wt_row, d_wt_val;
+      d_w_ptr, d_w_col, d_w_val, d_wide_slot, d_wide_row, d_wt_ptr, d_wt_row, d_wt_val, d_minv;
 };
 
 struct Plan {
@@ -185,7 +191,7 @@ struct Plan {
   std::vector<int32_t> h_ring_logM;
   int max_logM = 0;
   // per-call workspace (grown on demand)
-  DevBuf w_X, w_Y, w_H, w_T, w_D;
+  DevBuf w_X, w_Y, w_H, w_T, w_D, w_beta;
   FwdBlocks fb;
   std::vector<int32_t> h_btask_ptr;   // per block: [fwd, corr, end) offsets into d_btask
   DevBuf d_btask;
@@ -237,7 +243,9 @@ void batch_run(const osht_job_t* jobs, int n, hipStream_t stream, osht_graph_t**
 
 // GEMM (gemm.hip): tasks and descriptors already on the device.
 enum class GemmRole { Plan, ApplyInverse, ApplyForward, Correction, Adjoint };
-void launch_gemm(GemmRole role, const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st);
+// With e0/e1, the events take the launch's start and end timestamps.
+void launch_gemm(GemmRole role, const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st,
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Builds tasks for descriptors (64 x 64 tiles).
 void gemm_tasks(const std::vector<GemmDesc>& descs, std::vector<GemmTask>& tasks);
 

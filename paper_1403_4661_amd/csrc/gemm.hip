@@ -33,6 +33,8 @@
 
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 
 namespace osht {
@@ -387,9 +389,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
   }
 }
 
+// With events, they take the dispatch's own start and end timestamps
+// (hipExtLaunchKernel), so timing adds no packets between launches.
 template <bool ARF, bool BCF, class Role>
-void launch(const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st) {
-  hipLaunchKernelGGL((gemm_kernel<ARF, BCF, Role>), dim3(ntask), dim3(256), 0, st, d_desc, d_task);
+void launch(const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st, hipEvent_t e0,
+            hipEvent_t e1) {
+  if (e0) {
+    void* args[] = {(void*)&d_desc, (void*)&d_task};
+    OSHT_HIP(hipExtLaunchKernel((const void*)gemm_kernel<ARF, BCF, Role>, dim3(ntask), dim3(256), args, 0, st, e0, e1,
+                                0));
+  } else {
+    hipLaunchKernelGGL((gemm_kernel<ARF, BCF, Role>), dim3(ntask), dim3(256), 0, st, d_desc, d_task);
+  }
 }
 
 }  // namespace
@@ -403,14 +414,15 @@ void gemm_tasks(const std::vector<GemmDesc>& descs, std::vector<GemmTask>& tasks
   }
 }
 
-void launch_gemm(GemmRole role, const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st) {
+void launch_gemm(GemmRole role, const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st,
+                 hipEvent_t e0, hipEvent_t e1) {
   if (ntask <= 0) return;
   switch (role) {
-    case GemmRole::Plan: launch<true, false, RolePlan>(d_desc, d_task, ntask, st); break;
-    case GemmRole::ApplyInverse: launch<true, true, RoleApplyInverse>(d_desc, d_task, ntask, st); break;
-    case GemmRole::ApplyForward: launch<true, true, RoleApplyForward>(d_desc, d_task, ntask, st); break;
-    case GemmRole::Correction: launch<true, true, RoleCorrection>(d_desc, d_task, ntask, st); break;
-    case GemmRole::Adjoint: launch<false, true, RoleAdjoint>(d_desc, d_task, ntask, st); break;
+    case GemmRole::Plan: launch<true, false, RolePlan>(d_desc, d_task, ntask, st, e0, e1); break;
+    case GemmRole::ApplyInverse: launch<true, true, RoleApplyInverse>(d_desc, d_task, ntask, st, e0, e1); break;
+    case GemmRole::ApplyForward: launch<true, true, RoleApplyForward>(d_desc, d_task, ntask, st, e0, e1); break;
+    case GemmRole::Correction: launch<true, true, RoleCorrection>(d_desc, d_task, ntask, st, e0, e1); break;
+    case GemmRole::Adjoint: launch<false, true, RoleAdjoint>(d_desc, d_task, ntask, st, e0, e1); break;
   }
   OSHT_HIP(hipGetLastError());
 }

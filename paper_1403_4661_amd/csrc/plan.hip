@@ -337,7 +337,8 @@ int64_t Plan::device_bytes() const {
                           &d_twiddle, &d_chirp_tab, &w_X, &w_Y, &w_H, &w_T, &w_D, &d_gdesc, &d_gtask, &d_btask,
                           &fb.d_slot_list, &fb.d_lev_ptr, &fb.d_unk_slot, &fb.d_unk_r, &fb.d_unk_m, &fb.d_src_ptr,
                           &fb.d_src_slot, &fb.d_src_row, &fb.d_src_m, &fb.d_w_ptr, &fb.d_w_col, &fb.d_w_val,
-                          &fb.d_wide_slot, &fb.d_wide_row})
+                          &fb.d_wide_slot, &fb.d_wide_row, &fb.d_wt_ptr, &fb.d_wt_row, &fb.d_wt_val, &fb.d_minv,
+                          &w_beta, &d_atask})
     n += b->bytes;
   return (int64_t)n;
 }
@@ -442,6 +443,9 @@ void build_plan(Plan& p) {
   int b = p.L >= 768 ? 48 : 32;
   const char* env = std::getenv("OSHT_FWD_BLOCK");
   if (env) b = std::max(1, std::atoi(env));
+  // OSHT_DELTA_DENSE=0: level-by-level substitution instead of the
+  // precomputed (I + W)^{-1}
+  if (const char* ed = std::getenv("OSHT_DELTA_DENSE")) p.fb.dense = std::atoi(ed) != 0;
   while (!fwd_blocks_fit(p, b) && b > 1) b = std::max(1, b * 3 / 4);
   if (p.fp32) {
     // FP32 copies at the same element offsets.  A_m is released; Q_m stays

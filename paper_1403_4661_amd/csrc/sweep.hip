@@ -231,6 +231,94 @@ __global__ __launch_bounds__(512) void delta_solve_kernel(Geo g, int u0, int nu,
   }
 }
 
+// The same unknowns through the block's precomputed inverse:
+// delta = (I + W)^{-1} beta.  First beta[u][j] (2B columns per unknown) from
+// the alias rows of the sources, then one FP64 matrix-core product per block.
+__global__ __launch_bounds__(256) void delta_beta_kernel(Geo g, int u0, int nu, const int32_t* __restrict__ src_ptr,
+                                                         const int32_t* __restrict__ src_slot,
+                                                         const int32_t* __restrict__ src_row,
+                                                         const int32_t* __restrict__ src_m,
+                                                         const double* __restrict__ Y, double* __restrict__ beta) {
+  const int J = 2 * g.B;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)nu * J) return;
+  const int ul = (int)(e / J), j = (int)(e - (int64_t)ul * J);
+  const int u = u0 + ul;
+  double acc = 0.0;
+  for (int s = src_ptr[u]; s < src_ptr[u + 1]; ++s)
+    acc += Y[((int64_t)src_slot[s] * g.L + src_row[s]) * g.ncols + order_col(g, src_m[s], j)];
+  beta[e] = acc;
+}
+
+// delta (nu x 2B) = Minv (nu x nu, lower triangular, column-major, leading
+// dimension ld) * beta (nu x 2B, row-major), scattered into D[slot][r][col].
+// Workgroup (blockIdx.x, blockIdx.y) computes rows [16x, 16x + 16) and
+// columns [32y, 32y + 32) with v_mfma_f64_16x16x4f64: its 16 waves split the
+// k range [0, 16x + 16) (the triangle) into equal chunks, and the partial
+// tiles are summed in LDS in wave order.
+constexpr int kDeltaWaves = 16;
+__global__ __launch_bounds__(64 * kDeltaWaves) void delta_apply_kernel(
+    Geo g, int u0, int nu, const double* __restrict__ Minv, int ld, const double* __restrict__ beta,
+    const int32_t* __restrict__ unk_slot, const int32_t* __restrict__ unk_r, const int32_t* __restrict__ unk_m,
+    double* __restrict__ D, int bD) {
+  typedef double dbl4 __attribute__((ext_vector_type(4)));
+  __shared__ double red[kDeltaWaves][2][16][16];
+  const int J = 2 * g.B;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row0 = blockIdx.x * 16, col0 = blockIdx.y * 32;
+  const int kt = min(nu, row0 + 16);
+  const int chunk = ((kt + kDeltaWaves - 1) / kDeltaWaves + 3) & ~3;
+  const int kb = wave * chunk, ke = min(kt, kb + chunk);
+  const int r = row0 + (lane & 15), q = lane >> 4;
+  const int c0 = col0 + (lane & 15), c1 = c0 + 16;
+  const bool rok = r < nu, c0ok = c0 < J, c1ok = c1 < J;
+  dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  int k0 = kb;
+  // four k-steps per iteration, loads first
+  for (; k0 + 16 <= ke; k0 += 16) {
+    double a[4], b0[4], b1[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = k0 + 4 * t + q;
+      a[t] = rok ? Minv[(int64_t)k * ld + r] : 0.0;
+      b0[t] = c0ok ? beta[(int64_t)k * J + c0] : 0.0;
+      b1[t] = c1ok ? beta[(int64_t)k * J + c1] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b0[t], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b1[t], acc1, 0, 0, 0);
+    }
+  }
+  for (; k0 < ke; k0 += 4) {
+    const int k = k0 + q;
+    const bool kok = k < ke;
+    const double a = (rok && kok) ? Minv[(int64_t)k * ld + r] : 0.0;
+    const double b0 = (c0ok && kok) ? beta[(int64_t)k * J + c0] : 0.0;
+    const double b1 = (c1ok && kok) ? beta[(int64_t)k * J + c1] : 0.0;
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+  }
+  // accumulator register v of lane l holds row l / 16 + 4 v, column l % 16
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    red[wave][0][q + 4 * v][lane & 15] = acc0[v];
+    red[wave][1][q + 4 * v][lane & 15] = acc1[v];
+  }
+  __syncthreads();
+  if (threadIdx.x < 512) {
+    const int ct = threadIdx.x >> 8, i = (threadIdx.x >> 4) & 15, c = threadIdx.x & 15;
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < kDeltaWaves; ++w) sum += red[w][ct][i][c];
+    const int ul = row0 + i, j = col0 + 16 * ct + c;
+    if (ul < nu && j < J) {
+      const int u = u0 + ul;
+      D[((int64_t)unk_slot[u] * bD + unk_r[u]) * g.ncols + order_col(g, unk_m[u], j)] = sum;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- adjoint
 // The adjoint of the blocked forward runs the blocks in ascending order.
 // For block [q0, q1) with y_m = Q_m (h_m - E delta), delta = (I + W)^{-1} A Q h:
@@ -366,6 +454,62 @@ template <class T>
 void put_vec(DevBuf& d, const std::vector<T>& h) {
   d.alloc(std::max<size_t>(h.size(), 1) * sizeof(T));
   if (!h.empty()) OSHT_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+}  // namespace
+
+namespace {
+
+// (I + W)^{-1} of every block, by rows: with M = (I + W)^{-1}, M = I - W M,
+// and W only couples an unknown to unknowns of earlier (higher) levels, so
+// row u of M is e_u minus the W-weighted rows of M already computed.  The
+// product runs in FP64 on the host, once per block structure; M is lower
+// triangular and is stored column-major for the device product.
+void build_delta_inverses(Plan& p) {
+  FwdBlocks& fb = p.fb;
+  const int nblk = (int)fb.q0.size();
+  if (!fb.dense) {
+    fb.minv_off.clear();
+    fb.minv_ld.clear();
+    fb.d_minv.release();
+    return;
+  }
+  fb.minv_off.assign(nblk + 1, 0);
+  fb.minv_ld.assign(nblk, 0);
+  int64_t tot = 0;
+  for (int blk = 0; blk < nblk; ++blk) {
+    const int nu = fb.unk_ptr[blk + 1] - fb.unk_ptr[blk];
+    fb.minv_ld[blk] = (int32_t)round_up(std::max(nu, 1), 16);
+    fb.minv_off[blk] = tot;
+    tot += (int64_t)fb.minv_ld[blk] * nu;
+  }
+  fb.minv_off[nblk] = tot;
+  fb.d_minv.alloc(sizeof(double) * (size_t)std::max<int64_t>(tot, 1));
+  const int64_t nw = fb.w_ptr.back();
+  std::vector<double> wv((size_t)nw);
+  if (nw > 0) OSHT_HIP(hipMemcpy(wv.data(), fb.d_w_val.p, sizeof(double) * nw, hipMemcpyDeviceToHost));
+  std::vector<double> Mr, Mt;
+  for (int blk = 0; blk < nblk; ++blk) {
+    const int u0 = fb.unk_ptr[blk], nu = fb.unk_ptr[blk + 1] - u0, ld = fb.minv_ld[blk];
+    if (nu == 0) continue;
+    Mr.assign((size_t)nu * nu, 0.0);
+    for (int ul = 0; ul < nu; ++ul) {
+      double* row = &Mr[(size_t)ul * nu];
+      row[ul] = 1.0;
+      for (int64_t w = fb.w_ptr[u0 + ul]; w < fb.w_ptr[u0 + ul + 1]; ++w) {
+        const int c = fb.w_col[w];
+        OSHT_CHECK(c < ul, OSHT_ENOTSUP, "alias system not ordered by level");
+        const double x = wv[(size_t)w];
+        const double* rc = &Mr[(size_t)c * nu];
+        for (int q = 0; q <= c; ++q) row[q] -= x * rc[q];
+      }
+    }
+    Mt.assign((size_t)ld * nu, 0.0);
+    for (int ul = 0; ul < nu; ++ul)
+      for (int q = 0; q <= ul; ++q) Mt[(size_t)q * ld + ul] = Mr[(size_t)ul * nu + q];
+    OSHT_HIP(hipMemcpy(fb.d_minv.as<double>() + fb.minv_off[blk], Mt.data(), sizeof(double) * Mt.size(),
+                       hipMemcpyHostToDevice));
+  }
 }
 
 }  // namespace
@@ -506,6 +650,7 @@ void build_fwd_blocks(Plan& p, int b) {
   }
   fb.w_idx.clear();
   fb.w_idx.shrink_to_fit();
+  build_delta_inverses(p);
   const int64_t nwt = (int64_t)fb.wt_idx.size();
   fb.d_wt_val.alloc(std::max<int64_t>(nwt, 1) * sizeof(double));
   if (nwt > 0) {
@@ -569,7 +714,19 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
       const int64_t nw = fb.w_ptr[u0 + nu] - fb.w_ptr[u0];
       const int cpw = fb.cpw;
       const size_t lds = sizeof(double) * ((size_t)nu * cpw + nw) + sizeof(int32_t) * (nw + nu + 1);
-      {
+      if (fb.dense) {
+        ProfScope ps(p.prof, "delta_solve", st);
+        const int J = 2 * (int)B;
+        hipLaunchKernelGGL(delta_beta_kernel, dim3((unsigned)ceil_div((int64_t)nu * J, 256)), dim3(256), 0, st, g, u0,
+                           nu, fb.d_src_ptr.as<int32_t>(), fb.d_src_slot.as<int32_t>(), fb.d_src_row.as<int32_t>(),
+                           fb.d_src_m.as<int32_t>(), p.w_Y.as<double>(), p.w_beta.as<double>());
+        OSHT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(delta_apply_kernel, dim3((unsigned)ceil_div(nu, 16), (unsigned)ceil_div(J, 32)),
+                           dim3(64 * kDeltaWaves), 0, st, g, u0, nu, fb.d_minv.as<double>() + fb.minv_off[blk],
+                           fb.minv_ld[blk], p.w_beta.as<double>(), fb.d_unk_slot.as<int32_t>(),
+                           fb.d_unk_r.as<int32_t>(), fb.d_unk_m.as<int32_t>(), p.w_D.as<double>(), bD);
+        OSHT_HIP(hipGetLastError());
+      } else {
         ProfScope ps(p.prof, "delta_solve", st);
         hipLaunchKernelGGL(delta_solve_kernel, dim3((unsigned)ceil_div(2 * B, cpw)), dim3(512), lds, st, g, u0, nu,
                            lv1 - lv0 - 1, cpw, fb.d_lev_ptr.as<int32_t>() + lv0, fb.d_unk_slot.as<int32_t>(),
@@ -677,6 +834,7 @@ void tune_forward_blocks(Plan& p) {
   p.w_Y.release();
   p.w_H.release();
   p.w_D.release();
+  p.w_beta.release();
 }
 
 void run_forward_adjoint_blocked(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st) {

@@ -190,11 +190,13 @@ void ensure_workspace(Plan& p, int64_t B) {
   const size_t xy = sizeof(double) * (size_t)p.nslots * p.L * ncols;
   const size_t hb = sizeof(double) * 2 * (size_t)p.L * p.L * B;
   const size_t db = sizeof(double) * (size_t)p.nslots * std::max(p.fb.b, 1) * ncols;
-  const bool grow = (xy > p.w_X.bytes) || (hb > p.w_H.bytes) || (db > p.w_D.bytes);
+  const size_t bb = sizeof(double) * (size_t)std::max(p.fb.max_unk, 1) * 2 * B;
+  const bool grow = (xy > p.w_X.bytes) || (hb > p.w_H.bytes) || (db > p.w_D.bytes) || (bb > p.w_beta.bytes);
   p.w_X.reserve(xy);
   p.w_Y.reserve(xy);
   p.w_H.reserve(hb);
   p.w_D.reserve(db);
+  p.w_beta.reserve(bb);
   if (!grow && p.ws_batch == B && !p.h_gdesc.empty()) return;
   // descriptor tables are rewritten below: earlier work on any stream may
   // still read them
@@ -335,7 +337,12 @@ void launch_coef_to_slots(const Plan& p, const double* flm, double* X, int64_t B
 void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, GemmRole role, const char* prof_name,
                        hipStream_t st) {
   if (count <= 0) return;
-  ProfScope ps(p.prof, prof_name, st);
+  if (p.prof.wants(prof_name)) {
+    hipEvent_t e0 = p.prof.get(), e1 = p.prof.get();
+    launch_gemm(role, p.d_gdesc.as<GemmDesc>(), d_tasks, count, st, e0, e1);
+    p.prof.stat(prof_name).pending.emplace_back(e0, e1);
+    return;
+  }
   launch_gemm(role, p.d_gdesc.as<GemmDesc>(), d_tasks, count, st);
 }
 
