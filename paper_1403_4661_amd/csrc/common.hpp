@@ -93,7 +93,7 @@ struct GemmDesc {
   int32_t fp32;   // A is float (else double)
   double alpha, beta;
   int32_t m_lo;   // rows [m_lo, M) are computed and stored (tiles start at m_lo / 64)
-  int32_t pad;
+  int32_t b32;    // B is float (else double); GemmRole::ApplyInverse32 only
 };
 
 struct GemmTask {
@@ -242,7 +242,8 @@ void prepare_transforms(Plan& p, int64_t B);
 void batch_run(const osht_job_t* jobs, int n, hipStream_t stream, osht_graph_t** graph_inout);
 
 // GEMM (gemm.hip): tasks and descriptors already on the device.
-enum class GemmRole { Plan, ApplyInverse, ApplyForward, Correction, Adjoint };
+// ApplyInverse32: FP32 A and FP32 B (the inverse apply of FP32 plans).
+enum class GemmRole { Plan, ApplyInverse, ApplyInverse32, ApplyForward, Correction, Adjoint };
 // With e0/e1, the events take the launch's start and end timestamps.
 void launch_gemm(GemmRole role, const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st,
                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

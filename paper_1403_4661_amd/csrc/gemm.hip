@@ -44,6 +44,7 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 
 struct RolePlan {};
 struct RoleApplyInverse {};
+struct RoleApplyInverse32 {};
 struct RoleApplyForward {};
 struct RoleCorrection {};
 struct RoleAdjoint {};
@@ -196,25 +197,27 @@ __device__ __align__(16) double g_gemm_zero[2];
 constexpr int TKS = 16;  // k-tile depth
 constexpr int NST = 3;   // pipeline stages
 
-template <class T, int TK = TKS>
+template <class T, int TK = TKS, class TB = double>
 struct StreamShape {
   static constexpr int ES = sizeof(T);
   static constexpr int LPC = 64 * ES / 16;        // lanes per A column (32 | 16)
   static constexpr int CPI = 64 / LPC;            // A columns per wave load (2 | 4)
   static constexpr int NIA = TK / CPI;            // wave loads per A tile (8 | 4 at TK = 16)
-  static constexpr int NIB = TK / 2;              // wave loads per B tile (2 FP64 rows each)
+  static constexpr int EB = sizeof(TB);
+  static constexpr int LPR = 64 * EB / 16;        // lanes per B row (32 | 16)
+  static constexpr int RPI = 64 / LPR;            // B rows per wave load (2 | 4)
+  static constexpr int NIB = TK / RPI;            // wave loads per B tile
   static constexpr int PER_WAVE = (NIA + NIB) / 4;
   static constexpr int A_BYTES = 64 * TK * ES;
-  static constexpr int STAGE = A_BYTES + TK * 64 * 8;
+  static constexpr int STAGE = A_BYTES + TK * 64 * EB;
   static __device__ __forceinline__ int aswz(int k) { return ES == 8 ? 16 * (k & 1) : 16 * (k & 3); }
+  static __device__ __forceinline__ int bswz(int k) { return EB == 8 ? 16 * (k & 1) : 16 * (k & 3); }
 };
 
-__device__ __forceinline__ int bswz(int k) { return 16 * (k & 1); }
-
-template <class T, int TK = TKS>
+template <class T, int TK = TKS, class TB = double>
 __device__ __forceinline__ void stream_issue(const GemmDesc& d, const T* __restrict__ A, int m0, int n0, int k0,
                                              char* stage) {
-  typedef StreamShape<T, TK> S;
+  typedef StreamShape<T, TK, TB> S;
   typedef __attribute__((address_space(3))) void* lds_ptr;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // A: column c of the tile holds rows m0..m0+63, row r at position r ^ aswz(k)
@@ -229,13 +232,14 @@ __device__ __forceinline__ void stream_issue(const GemmDesc& d, const T* __restr
   }
   // B: row kk of the tile holds columns n0..n0+63, column j at position j ^ bswz(k)
   char* bst = stage + S::A_BYTES;
+  const TB* __restrict__ Bp = reinterpret_cast<const TB*>(d.B);
 #pragma unroll
   for (int i = wave; i < S::NIB; i += 4) {
-    const int kk = 2 * i + lane / 32;
-    const int pos = (lane % 32) * 2;
+    const int kk = S::RPI * i + lane / S::LPR;
+    const int pos = (lane % S::LPR) * (16 / S::EB);
     const int k = k0 + kk;
-    const int j = n0 + (pos ^ bswz(k));
-    const void* src = (k < d.K && j < d.N) ? (const void*)(d.B + (int64_t)k * d.sBr + j) : (const void*)g_gemm_zero;
+    const int j = n0 + (pos ^ S::bswz(k));
+    const void* src = (k < d.K && j < d.N) ? (const void*)(Bp + (int64_t)k * d.sBr + j) : (const void*)g_gemm_zero;
     __builtin_amdgcn_global_load_lds(src, (lds_ptr)(bst + i * 1024), 16, 0, 0);
   }
 }
@@ -264,9 +268,9 @@ __device__ __forceinline__ void wait_vm(int n) {
   }
 }
 
-template <class T, int TK = TKS, int NS = NST>
+template <class T, int TK = TKS, int NS = NST, class TB = double>
 __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTask& t, char* smem) {
-  typedef StreamShape<T, TK> S;
+  typedef StreamShape<T, TK, TB> S;
   constexpr bool F64 = sizeof(T) == 8;
   const T* __restrict__ A = static_cast<const T*>(d.A);
   const int m0 = t.mt * TM, n0 = t.nt * TN;
@@ -278,7 +282,7 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
   const int nt = (d.K + TK - 1) / TK;
 #pragma unroll
   for (int st = 0; st < NS - 1; ++st)
-    if (st < nt) stream_issue<T, TK>(d, A, m0, n0, st * TK, smem + st * S::STAGE);
+    if (st < nt) stream_issue<T, TK, TB>(d, A, m0, n0, st * TK, smem + st * S::STAGE);
   for (int kt = 0; kt < nt; ++kt) {
     // tiles issued after kt: min(NS-2, nt-1-kt) before this iteration's issue
     const int ahead = min(NS - 2, nt - 1 - kt);
@@ -286,10 +290,11 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
     // tile kt complete in LDS, tile kt-1's stage free.  A bare barrier: a
     // fence here would also wait for the loads still in flight.
     __builtin_amdgcn_s_barrier();
-    if (kt + NS - 1 < nt) stream_issue<T, TK>(d, A, m0, n0, (kt + NS - 1) * TK, smem + ((kt + NS - 1) % NS) * S::STAGE);
+    if (kt + NS - 1 < nt)
+      stream_issue<T, TK, TB>(d, A, m0, n0, (kt + NS - 1) * TK, smem + ((kt + NS - 1) % NS) * S::STAGE);
     const char* stage = smem + (kt % NS) * S::STAGE;
     const T* As = reinterpret_cast<const T*>(stage);
-    const double* Bs = reinterpret_cast<const double*>(stage + S::A_BYTES);
+    const TB* Bs = reinterpret_cast<const TB*>(stage + S::A_BYTES);
     if constexpr (F64) {
 #pragma unroll
       for (int s = 0; s < TK / 4; ++s) {
@@ -297,7 +302,7 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
         const double a = As[k * 64 + ((wave * 16 + li) ^ S::aswz(k))];
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
-          const double b = Bs[k * 64 + ((nb * 16 + li) ^ bswz(k))];
+          const double b = Bs[k * 64 + ((nb * 16 + li) ^ S::bswz(k))];
           acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[nb], 0, 0, 0);
         }
       }
@@ -311,7 +316,7 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
         const float a = As[k * 64 + ((wave * 16 + li) ^ S::aswz(k))];
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
-          const float b = (float)Bs[k * 64 + ((nb * 16 + li) ^ bswz(k))];
+          const float b = (float)Bs[k * 64 + ((nb * 16 + li) ^ S::bswz(k))];
           c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c[nb], 0, 0, 0);
         }
         if (TK > 16 && s % 4 == 3 && s + 1 < TK / 4) {  // FP32 partial sums cover 16 k at most
@@ -354,14 +359,19 @@ static_assert(2 * TK * (TM + Pad<float>::v) * 2 * sizeof(float) <= kSmemDoubles 
 // forward's per-block launches (few workgroups each) 16-deep tiles in 3.
 template <class Role> struct StreamCfg { static constexpr int TK = 16, NS = 3; };
 template <> struct StreamCfg<RoleApplyInverse> { static constexpr int TK = 32, NS = 2; };
+template <> struct StreamCfg<RoleApplyInverse32> { static constexpr int TK = 32, NS = 2; };
 
 // Each task's descriptor selects the matrix precision (GemmDesc::fp32).
 template <bool ARF, bool BCF, class Role>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs,
                                                    const GemmTask* __restrict__ tasks) {
   typedef StreamCfg<Role> SC;
-  constexpr int kStream = SC::NS * StreamShape<double, SC::TK>::STAGE / 8;
-  __shared__ __align__(16) double smem[(ARF && BCF) ? (kStream > kSmemDoubles ? kStream : kSmemDoubles) : kSmemDoubles];
+  constexpr bool kF32 = std::is_same<Role, RoleApplyInverse32>::value;
+  constexpr int kStream =
+      SC::NS * (kF32 ? StreamShape<float, SC::TK, float>::STAGE : StreamShape<double, SC::TK>::STAGE) / 8;
+  __shared__ __align__(16) double smem[kF32 ? kStream
+                                             : (ARF && BCF) ? (kStream > kSmemDoubles ? kStream : kSmemDoubles)
+                                                            : kSmemDoubles];
   // Workgroups are dispatched round-robin over the 8 XCDs.  Tasks come in
   // descriptor order, the M tiles of one descriptor (which share its B panel)
   // adjacent; runs of 16 consecutive tasks go to workgroups of one XCD, so a
@@ -380,7 +390,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
   const GemmTask t = tasks[ti];
   const GemmDesc d = descs[t.desc];
   // column-major A streams through LDS
-  if constexpr (ARF && BCF) {
+  if constexpr (kF32) {
+    gemm_tile_stream<float, SC::TK, SC::NS, float>(d, t, reinterpret_cast<char*>(smem));
+  } else if constexpr (ARF && BCF) {
     if (d.fp32) gemm_tile_stream<float, SC::TK, SC::NS>(d, t, reinterpret_cast<char*>(smem));
     else gemm_tile_stream<double, SC::TK, SC::NS>(d, t, reinterpret_cast<char*>(smem));
   } else {
@@ -420,6 +432,7 @@ void launch_gemm(GemmRole role, const GemmDesc* d_desc, const GemmTask* d_task, 
   switch (role) {
     case GemmRole::Plan: launch<true, false, RolePlan>(d_desc, d_task, ntask, st, e0, e1); break;
     case GemmRole::ApplyInverse: launch<true, true, RoleApplyInverse>(d_desc, d_task, ntask, st, e0, e1); break;
+    case GemmRole::ApplyInverse32: launch<true, true, RoleApplyInverse32>(d_desc, d_task, ntask, st, e0, e1); break;
     case GemmRole::ApplyForward: launch<true, true, RoleApplyForward>(d_desc, d_task, ntask, st, e0, e1); break;
     case GemmRole::Correction: launch<true, true, RoleCorrection>(d_desc, d_task, ntask, st, e0, e1); break;
     case GemmRole::Adjoint: launch<false, true, RoleAdjoint>(d_desc, d_task, ntask, st, e0, e1); break;

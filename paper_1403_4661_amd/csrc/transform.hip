@@ -39,9 +39,11 @@ namespace {
 // else:     flm[b][l^2 + l + m] = sign(m) * Y[slot(m)][l - l0(m)][col(m, b)],
 //           zero when l < l0(m) (spin: degrees below |s|).
 // sign(m) = (-1)^|m| for spin 0 and m < 0 (both orders share A_|m|, Q_|m|).
-template <bool TO_SLOTS>
+// With TO_SLOTS the slot values are written as O (double2, or float2 for
+// the FP32 inverse apply, which rounds its right-hand side to FP32).
+template <bool TO_SLOTS, class O = double2>
 __global__ __launch_bounds__(256) void coef_transpose_kernel(Geo g, const double2* __restrict__ src,
-                                                             double2* __restrict__ dst) {
+                                                             O* __restrict__ dst) {
   __shared__ double2 tile[16][65];
   const int l = blockIdx.y;
   const int nc = g.ncols >> 1;
@@ -53,7 +55,7 @@ __global__ __launch_bounds__(256) void coef_transpose_kernel(Geo g, const double
     const int nm = min(64, l - m0 + 1);
     for (int b0 = 0; b0 < g.B; b0 += 16) {
       const int nb = min(16, g.B - b0);
-      if (TO_SLOTS) {
+      if constexpr (TO_SLOTS) {
         for (int e = threadIdx.x; e < nb * nm; e += blockDim.x) {
           const int bb = e / nm, mi = e - bb * nm;
           tile[bb][mi] = src[(int64_t)(b0 + bb) * LL + (int64_t)l * l + l + m0 + mi];
@@ -68,7 +70,10 @@ __global__ __launch_bounds__(256) void coef_transpose_kernel(Geo g, const double
           const int sgn = (g.s == 0 && m < 0) ? 1 : 0;
           double2 v = tile[bb][mi];
           if (sgn && (am & 1)) { v.x = -v.x; v.y = -v.y; }
-          dst[((int64_t)slot * g.L + (l - l0)) * nc + sgn * g.B + b0 + bb] = v;
+          O o;
+          o.x = v.x;
+          o.y = v.y;
+          dst[((int64_t)slot * g.L + (l - l0)) * nc + sgn * g.B + b0 + bb] = o;
         }
       } else {
         for (int e = threadIdx.x; e < nm * nb; e += blockDim.x) {
@@ -240,7 +245,13 @@ void ensure_workspace(Plan& p, int64_t B) {
         if (use32) d.A = (isA ? A32 : Q32) + off;
         else d.A = (isA ? A64 : Q64) + off;
       };
-      if (dir == kInv) { setA(f32, true, sl.offA); d.sAr = 1; d.sAc = sl.ldA; d.M = p.L; d.K = sl.K; }
+      if (dir == kInv) {
+        setA(f32, true, sl.offA); d.sAr = 1; d.sAc = sl.ldA; d.M = p.L; d.K = sl.K;
+        if (f32) {  // right-hand side written as FP32 into the same workspace
+          d.B = reinterpret_cast<const double*>(reinterpret_cast<const float*>(X) + (int64_t)i * p.L * ncols);
+          d.b32 = 1;
+        }
+      }
       if (dir == kIadj) { setA(f32, true, sl.offA); d.sAr = sl.ldA; d.sAc = 1; d.M = sl.K; d.K = p.L; }
       if (dir == kFadj) { setA(false, false, sl.offQ); d.sAr = sl.ldQ; d.sAc = 1; d.M = sl.R; d.K = sl.K + am; }
       if (dir == kFadjCorr) {  // Z -= Q^T[:, K + q0 .. K + |m|) E, E rows k - q0
@@ -327,10 +338,15 @@ void launch_fwd_scatter(const Plan& p, const double* Y, double* flm, int64_t B, 
   OSHT_HIP(hipGetLastError());
 }
 
-void launch_coef_to_slots(const Plan& p, const double* flm, double* X, int64_t B, hipStream_t st) {
+void launch_coef_to_slots(const Plan& p, const double* flm, double* X, int64_t B, hipStream_t st, bool f32) {
   const Geo g = geo(p, B);
-  hipLaunchKernelGGL(coef_transpose_kernel<true>, dim3((unsigned)ceil_div(2 * p.L - 1, 64), p.L), dim3(256), 0, st, g,
-                     reinterpret_cast<const double2*>(flm), reinterpret_cast<double2*>(X));
+  const dim3 grid((unsigned)ceil_div(2 * p.L - 1, 64), p.L);
+  if (f32)
+    hipLaunchKernelGGL((coef_transpose_kernel<true, float2>), grid, dim3(256), 0, st, g,
+                       reinterpret_cast<const double2*>(flm), reinterpret_cast<float2*>(X));
+  else
+    hipLaunchKernelGGL((coef_transpose_kernel<true, double2>), grid, dim3(256), 0, st, g,
+                       reinterpret_cast<const double2*>(flm), reinterpret_cast<double2*>(X));
   OSHT_HIP(hipGetLastError());
 }
 
@@ -370,7 +386,7 @@ void gemm_slots(Plan& p, int dir, int s0, int s1, hipStream_t st) {
   int first, count;
   task_range(p, dir, s0, s1, first, count);
   // inverse / forward read A or Q column-major; the adjoints read them transposed
-  const GemmRole role = dir == kInv                        ? GemmRole::ApplyInverse
+  const GemmRole role = dir == kInv                        ? (p.fp32 ? GemmRole::ApplyInverse32 : GemmRole::ApplyInverse)
                         : (dir == kFwd || dir == kFwdAlias)  ? GemmRole::ApplyForward
                         : (dir == kCorr || dir == kCorrAlias) ? GemmRole::Correction
                                                               : GemmRole::Adjoint;
@@ -391,7 +407,7 @@ void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t s
   ensure_workspace(p, B);
   const Geo g = geo(p, B);
   (void)g;
-  launch_coef_to_slots(p, flm, p.w_X.as<double>(), B, st);
+  launch_coef_to_slots(p, flm, p.w_X.as<double>(), B, st, p.fp32);
   gemm_slots(p, kInv, 0, p.nslots, st);
   {
     ProfScope ps(p.prof, "fold", st);
