@@ -5,11 +5,13 @@ One step = one inverse SHT followed by one forward SHT of a batch of B maps
 spin 0, L = 1024, B = 16, coefficients N(0,1)(1+l)^-1 (seed 5).
 
 Two paths run on the same inputs, each timed over its own K steps:
-  mixed      FP32 plan: the inverse apply on FP32 A_m with FP32 matrix cores;
-             the forward sweep, ring DFTs and all buffers FP64;
+  mixed      OSHT_PREC_FP32_FWD plan: the inverse apply on FP32 A_m with an
+             FP32 right-hand side, and the forward apply's 64-row tiles of
+             P_m^{-1} rows on FP32 matrix cores; the tiles holding alias rows
+             A_m^top P_m^{-1} (which feed the descending-order chain), the
+             ring DFTs, the alias solves and all buffers FP64;
   fp64       FP64 throughout;
-  (mixed-fwd, optional: also the forward's P_m^{-1} rows on FP32 matrix
-             cores, alias rows FP64.)
+  (mixed-inv, optional: OSHT_PREC_FP32, FP32 on the inverse side only.)
 `value` is the mixed path's SHT/s; the fp64 path, the speedup and the
 errors of both paths are reported beside it.
 
@@ -41,7 +43,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X dense matrix FP64 / FP32
-PRECISION = {"mixed": "fp32", "mixed-fwd": "fp32-fwd", "fp64": "fp64"}
+PRECISION = {"mixed": "fp32-fwd", "mixed-inv": "fp32", "fp64": "fp64"}
 
 
 def parse():
@@ -118,22 +120,23 @@ def forward_apply_flops(L, B):
     """Algorithmic flops of the forward apply, split by the precision of the
     matrix rows: order |m| streams the L x (L-|m|) matrix
     [P^-1; A^top P^-1] against 4B real columns (spin 0 pairs +-m), 2 flops
-    per entry and column; the (L-|m|) x (L-|m|) block P^-1 is FP32 on the
-    mixed path, the |m| x (L-|m|) alias block A^top P^-1 always FP64.
-    Returns (coefficient-row flops, alias-row flops)."""
-    coef = sum(8.0 * B * (L - am) * (L - am) for am in range(L))
-    alias = sum(8.0 * B * am * (L - am) for am in range(L))
-    return coef, alias
+    per entry and column.  With FP32 coefficient rows (mixed) the
+    64-row tiles holding only rows of P^-1, rows [0, 64 floor((L-|m|)/64)),
+    run in FP32 and the rest (the boundary tile and A^top P^-1) in FP64.
+    Returns (flops of those FP32-capable rows, flops of the other rows)."""
+    f32 = sum(8.0 * B * ((L - am) // 64 * 64) * (L - am) for am in range(L))
+    f64 = sum(8.0 * B * (L - (L - am) // 64 * 64) * (L - am) for am in range(L))
+    return f32, f64
 
 
-def apply_peak(path, coef, alias):
+def apply_peak(path, f32, f64):
     """Matrix-core peak of the forward apply: FP64 78.6 TFLOP/s; with FP32
-    coefficient rows (mixed-fwd) the flop-weighted combination of FP32
-    (157.3) for those rows and FP64 (78.6) for the alias rows, i.e. total
-    flops over the time both parts would take at their peaks."""
-    if path != "mixed-fwd":
+    coefficient tiles (mixed) the flop-weighted combination of FP32
+    (157.3) for those tiles and FP64 (78.6) for the rest, i.e. total flops
+    over the time both parts would take at their peaks."""
+    if path != "mixed":
         return PEAK_TFLOPS["fp64"]
-    return (coef + alias) / (coef / PEAK_TFLOPS["fp32"] + alias / PEAK_TFLOPS["fp64"])
+    return (f32 + f64) / (f32 / PEAK_TFLOPS["fp32"] + f64 / PEAK_TFLOPS["fp64"])
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_forward_L1024_B16.md")
@@ -244,8 +247,8 @@ def main():
     out_paths = {}
     for name, r in res.items():
         ms_step = r["seconds"] / args.steps * 1e3
-        coef, alias = forward_apply_flops(L, B)
-        ach = (coef + alias) * args.steps / (r["apply_forward_ms"] * 1e-3) / 1e12 \
+        f32, f64 = forward_apply_flops(L, B)
+        ach = (f32 + f64) * args.steps / (r["apply_forward_ms"] * 1e-3) / 1e12 \
             if r["apply_forward_ms"] > 0 else 0.0
         out_paths[name] = {
             "sht_per_s": B * args.steps / r["seconds"],
@@ -254,7 +257,7 @@ def main():
             "max_rel_err_roundtrip": rel(r["g"], flm),
             "device_bytes": r["device_bytes"],
             "apply_forward": {"launches": r["apply_forward_launches"], "ms_total": r["apply_forward_ms"],
-                              "tflops": ach, "peak_tflops": apply_peak(name, coef, alias)},
+                              "tflops": ach, "peak_tflops": apply_peak(name, f32, f64)},
         }
     if "fp64" in res and len(res) > 1:
         for name in res:
@@ -293,7 +296,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "f32 inverse apply + f64", "mixed-fwd": "f32 applies + f64"}.get(head, "f64"),
+        "dtype": {"mixed": "f32 applies + f64", "mixed-inv": "f32 inverse apply + f64"}.get(head, "f64"),
         "data": "synthetic",
         "config": {"workload": f"spin-0 inverse then forward SHT, L={L}, batch {B}, flm N(0,1)(1+l)^-1 seed 5",
                    "L": L, "batch": B, "spin": 0, "path": head, "parallelism": "single-gpu"},

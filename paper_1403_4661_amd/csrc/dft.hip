@@ -37,7 +37,10 @@ namespace osht {
 
 namespace {
 
-struct cplx {
+// 16-byte aligned, so that LDS exchanges use 128-bit accesses: with 64-bit
+// halves, a 16-byte lane stride puts two lanes of a 16-lane group on each
+// bank pair.
+struct alignas(16) cplx {
   double x, y;
 };
 __device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }

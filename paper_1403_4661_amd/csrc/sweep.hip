@@ -273,31 +273,36 @@ __global__ __launch_bounds__(64 * kDeltaWaves) void delta_apply_kernel(
   const int c0 = col0 + (lane & 15), c1 = c0 + 16;
   const bool rok = r < nu, c0ok = c0 < J, c1ok = c1 < J;
   dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  int k0 = kb;
-  // four k-steps per iteration, loads first
-  for (; k0 + 16 <= ke; k0 += 16) {
-    double a[4], b0[4], b1[4];
+  // batches of four k-steps, double-buffered in registers: the loads of
+  // batch i + 1 are in flight while batch i runs on the matrix cores; k
+  // beyond the wave's range loads zeros
+  double a[2][4], b0[2][4], b1[2][4];
+  auto load = [&](double* pa, double* pb0, double* pb1, int kbase) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int k = k0 + 4 * t + q;
-      a[t] = rok ? Minv[(int64_t)k * ld + r] : 0.0;
-      b0[t] = c0ok ? beta[(int64_t)k * J + c0] : 0.0;
-      b1[t] = c1ok ? beta[(int64_t)k * J + c1] : 0.0;
+      const int k = kbase + 4 * t + q;
+      const bool kok = k < ke;
+      pa[t] = (rok && kok) ? Minv[(int64_t)k * ld + r] : 0.0;
+      pb0[t] = (c0ok && kok) ? beta[(int64_t)k * J + c0] : 0.0;
+      pb1[t] = (c1ok && kok) ? beta[(int64_t)k * J + c1] : 0.0;
     }
+  };
+  auto mfma4 = [&](const double* pa, const double* pb0, const double* pb1) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b0[t], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b1[t], acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[t], pb0[t], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[t], pb1[t], acc1, 0, 0, 0);
     }
-  }
-  for (; k0 < ke; k0 += 4) {
-    const int k = k0 + q;
-    const bool kok = k < ke;
-    const double a = (rok && kok) ? Minv[(int64_t)k * ld + r] : 0.0;
-    const double b0 = (c0ok && kok) ? beta[(int64_t)k * J + c0] : 0.0;
-    const double b1 = (c1ok && kok) ? beta[(int64_t)k * J + c1] : 0.0;
-    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+  };
+  const int nbat = ke > kb ? (ke - kb + 15) / 16 : 0;
+  if (nbat > 0) load(a[0], b0[0], b1[0], kb);
+  for (int i = 0; i < nbat; i += 2) {
+    if (i + 1 < nbat) load(a[1], b0[1], b1[1], kb + 16 * (i + 1));
+    mfma4(a[0], b0[0], b1[0]);
+    if (i + 1 < nbat) {
+      if (i + 2 < nbat) load(a[0], b0[0], b1[0], kb + 16 * (i + 2));
+      mfma4(a[1], b0[1], b1[1]);
+    }
   }
   // accumulator register v of lane l holds row l / 16 + 4 v, column l % 16
 #pragma unroll

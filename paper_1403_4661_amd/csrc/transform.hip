@@ -261,12 +261,17 @@ void ensure_workspace(Plan& p, int64_t B) {
         d.alpha = -1.0; d.beta = 1.0;
       }
       if (dir == kFwd || dir == kCorr || dir == kFwdAlias || dir == kCorrAlias) {
-        // rows [0, K) (coefficients) in the main descriptor, rows [K, K+|m|)
-        // (aliases) in the alias one when the plan is FP32
-        // descriptors keep column-base pointers and select rows by [m_lo, M)
+        // With FP32 coefficient rows: the 64-row tiles that hold only
+        // coefficient rows, [0, Kc) with Kc = 64 floor(K / 64), in the main
+        // descriptor (FP32), the rest [Kc, K + |m|) -- the tile straddling
+        // the coefficient/alias boundary and the alias rows -- in the alias
+        // one (FP64), so that every 64-row tile is computed once.  Otherwise
+        // all rows in the main descriptor.  Descriptors keep column-base
+        // pointers and select rows by [m_lo, M).
         const bool alias = dir == kFwdAlias || dir == kCorrAlias;
-        const int r0 = alias ? sl.K : 0;
-        const int r1 = f32q ? (alias ? sl.K + am : sl.K) : (alias ? 0 : sl.K + am);
+        const int Kc = sl.K / 64 * 64;
+        const int r0 = alias ? Kc : 0;
+        const int r1 = f32q ? (alias ? sl.K + am : Kc) : (alias ? 0 : sl.K + am);
         setA(f32q && !alias, false, sl.offQ);
         d.sAr = 1; d.sAc = sl.ldQ;
         d.m_lo = r1 > r0 ? r0 : 0;
