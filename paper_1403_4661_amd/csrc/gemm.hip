@@ -268,7 +268,10 @@ __device__ __forceinline__ void wait_vm(int n) {
   }
 }
 
-template <class T, int TK = TKS, int NS = NST, class TB = double>
+// PREFC: C is read (beta != 0) into registers before the k loop, so that its
+// latency overlaps the streaming instead of following it (the forward's
+// correction, whose k depth is at most one block of levels).
+template <class T, int TK = TKS, int NS = NST, class TB = double, bool PREFC = false>
 __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTask& t, char* smem) {
   typedef StreamShape<T, TK, TB> S;
   constexpr bool F64 = sizeof(T) == 8;
@@ -279,6 +282,20 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
   dbl4 acc[4];
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) acc[nb] = dbl4{0.0, 0.0, 0.0, 0.0};
+  double cpre[4][4];
+  if constexpr (PREFC) {
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + wave * 16 + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+        const int col = n0 + nb * 16 + (lane & 15);
+        cpre[nb][v] = (d.beta != 0.0 && r >= d.m_lo && r < d.M && col < d.N)
+                          ? d.C[(int64_t)r * d.sCr + (int64_t)col * d.sCc]
+                          : 0.0;
+      }
+    }
+  }
   const int nt = (d.K + TK - 1) / TK;
 #pragma unroll
   for (int st = 0; st < NS - 1; ++st)
@@ -343,7 +360,7 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
       if (r >= d.m_lo && r < d.M && col < d.N) {
         double* cp = d.C + (int64_t)r * d.sCr + (int64_t)col * d.sCc;
         double x = d.alpha * acc[nb][v];
-        if (d.beta != 0.0) x += d.beta * (*cp);
+        if (d.beta != 0.0) x += d.beta * (PREFC ? cpre[nb][v] : *cp);
         *cp = x;
       }
     }
@@ -393,8 +410,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
   if constexpr (kF32) {
     gemm_tile_stream<float, SC::TK, SC::NS, float>(d, t, reinterpret_cast<char*>(smem));
   } else if constexpr (ARF && BCF) {
-    if (d.fp32) gemm_tile_stream<float, SC::TK, SC::NS>(d, t, reinterpret_cast<char*>(smem));
-    else gemm_tile_stream<double, SC::TK, SC::NS>(d, t, reinterpret_cast<char*>(smem));
+    constexpr bool kPrefC = std::is_same<Role, RoleCorrection>::value;
+    if (d.fp32) gemm_tile_stream<float, SC::TK, SC::NS, double, kPrefC>(d, t, reinterpret_cast<char*>(smem));
+    else gemm_tile_stream<double, SC::TK, SC::NS, double, kPrefC>(d, t, reinterpret_cast<char*>(smem));
   } else {
     if (d.fp32) gemm_tile<ARF, BCF, float>(d, t, smem);
     else gemm_tile<ARF, BCF, double>(d, t, smem);
