@@ -57,9 +57,30 @@ __global__ __launch_bounds__(256) void block_gather_kernel(Geo g, const Slot* __
   const int bin = pmod(m, n);
   double2 v = H[((int64_t)k * k + bin) * g.B + b];
   const int start = bin - ((bin + g.L - 1) / n) * n;
-  for (int mp = start; mp <= g.L - 1; mp += n) {
+  // only orders solved in earlier blocks (|m'| >= q1); four loads in flight,
+  // an excluded entry loading Y[0] and subtracting nothing, so the
+  // subtractions keep ascending m' order
+  int mp = start;
+  for (; mp + 3 * n <= g.L - 1; mp += 4 * n) {
+    double2 a[4];
+    bool use[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int q = mp + t * n, aq = q < 0 ? -q : q;
+      use[t] = q != m && aq >= q1;
+      a[t] = *reinterpret_cast<const double2*>(Y + (use[t] ? alias_index(g, slots, q, k, b, 0) : 0));
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (use[t]) {
+        v.x -= a[t].x;
+        v.y -= a[t].y;
+      }
+    }
+  }
+  for (; mp <= g.L - 1; mp += n) {
     const int amp = mp < 0 ? -mp : mp;
-    if (mp == m || amp < q1) continue;  // only orders solved in earlier blocks
+    if (mp == m || amp < q1) continue;
     const double2 a = *reinterpret_cast<const double2*>(Y + alias_index(g, slots, mp, k, b, 0));
     v.x -= a.x;
     v.y -= a.y;
