@@ -149,9 +149,10 @@ struct FwdBlocks {
   int max_unk = 0;
   int64_t max_w = 0;                           // max W entries in one block
   int cpw = 1;                                 // delta-solve columns per workgroup
-  // (I + W)^{-1} of every block, column-major with leading dimension
-  // minv_ld[blk], at element offset minv_off[blk] of d_minv; the forward
-  // then takes delta = (I + W)^{-1} beta as one matrix product per block
+  // (I + W)^{-1} of every block with column u repeated for each source of
+  // unknown u, column-major with leading dimension minv_ld[blk], at element
+  // offset minv_off[blk] of d_minv; the forward then takes delta as one
+  // matrix product per block (d_src_yrow: the sources' alias rows)
   bool dense = true;
   std::vector<int64_t> minv_off;
   std::vector<int32_t> minv_ld;
@@ -167,7 +168,7 @@ struct FwdBlocks {
     max_unk = 0;
   }
   DevBuf d_slot_list, d_lev_ptr, d_unk_slot, d_unk_r, d_unk_m, d_src_ptr, d_src_slot, d_src_row, d_src_m,
-      d_w_ptr, d_w_col, d_w_val, d_wide_slot, d_wide_row, d_wt_ptr, d_wt_row, d_wt_val, d_minv;
+      d_w_ptr, d_w_col, d_w_val, d_wide_slot, d_wide_row, d_wt_ptr, d_wt_row, d_wt_val, d_minv, d_src_yrow;
 };
 
 struct Plan {
@@ -191,7 +192,7 @@ struct Plan {
   std::vector<int32_t> h_ring_logM;
   int max_logM = 0;
   // per-call workspace (grown on demand)
-  DevBuf w_X, w_Y, w_H, w_T, w_D, w_beta;
+  DevBuf w_X, w_Y, w_H, w_T, w_D;
   FwdBlocks fb;
   std::vector<int32_t> h_btask_ptr;   // per block: [fwd, corr, end) offsets into d_btask
   DevBuf d_btask;

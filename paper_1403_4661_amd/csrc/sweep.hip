@@ -253,41 +253,31 @@ __global__ __launch_bounds__(512) void delta_solve_kernel(Geo g, int u0, int nu,
 }
 
 // The same unknowns through the block's precomputed inverse:
-// delta = (I + W)^{-1} beta.  First beta[u][j] (2B columns per unknown) from
-// the alias rows of the sources, then one FP64 matrix-core product per block.
-__global__ __launch_bounds__(256) void delta_beta_kernel(Geo g, int u0, int nu, const int32_t* __restrict__ src_ptr,
-                                                         const int32_t* __restrict__ src_slot,
-                                                         const int32_t* __restrict__ src_row,
-                                                         const int32_t* __restrict__ src_m,
-                                                         const double* __restrict__ Y, double* __restrict__ beta) {
-  const int J = 2 * g.B;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)nu * J) return;
-  const int ul = (int)(e / J), j = (int)(e - (int64_t)ul * J);
-  const int u = u0 + ul;
-  double acc = 0.0;
-  for (int s = src_ptr[u]; s < src_ptr[u + 1]; ++s)
-    acc += Y[((int64_t)src_slot[s] * g.L + src_row[s]) * g.ncols + order_col(g, src_m[s], j)];
-  beta[e] = acc;
-}
-
-// delta (nu x 2B) = Minv (nu x nu, lower triangular, column-major, leading
-// dimension ld) * beta (nu x 2B, row-major), scattered into D[slot][r][col].
-// Workgroup (blockIdx.x, blockIdx.y) computes rows [16x, 16x + 16) and
-// columns [32y, 32y + 32) with v_mfma_f64_16x16x4f64: its 16 waves split the
-// k range [0, 16x + 16) (the triangle) into equal chunks, and the partial
-// tiles are summed in LDS in wave order.
+// delta = (I + W)^{-1} beta, beta_u the sum of the alias values of u's
+// sources.  With the inverse's column u repeated for every source of u
+// (Minv_s, one column per source, sources ordered by their unknown),
+// delta = Minv_s s, s the vector of the sources' alias values: one FP64
+// matrix-core product that reads the alias rows of Y directly.
+//
+// Rows are unknowns, k runs over the block's sources s (global index s0 + k):
+// A[r][k] = Minv_s[k * ld + r] (column-major, lower triangular in the
+// unknown order), B[k][j] = Y[row(s) * ncols + order_col(m_s, j)] with
+// src_yrow[s] = 2 row(s) + (m_s < 0 on spin 0).  Workgroup (x, y) computes
+// unknowns [16x, 16x + 16) and columns [32y, 32y + 32) of the 2B map-part
+// columns; its waves split the sources [0, src_ptr[u0 + 16x + 16] - s0) (the
+// triangle) into equal chunks, and the partial tiles are summed in LDS in
+// wave order.  Writes delta into D[slot][r][col].
 constexpr int kDeltaWaves = 16;
 __global__ __launch_bounds__(64 * kDeltaWaves) void delta_apply_kernel(
-    Geo g, int u0, int nu, const double* __restrict__ Minv, int ld, const double* __restrict__ beta,
-    const int32_t* __restrict__ unk_slot, const int32_t* __restrict__ unk_r, const int32_t* __restrict__ unk_m,
-    double* __restrict__ D, int bD) {
+    Geo g, int u0, int nu, int s0, const int32_t* __restrict__ src_ptr, const int32_t* __restrict__ src_yrow,
+    const double* __restrict__ Minv, int ld, const double* __restrict__ Y, const int32_t* __restrict__ unk_slot,
+    const int32_t* __restrict__ unk_r, const int32_t* __restrict__ unk_m, double* __restrict__ D, int bD) {
   typedef double dbl4 __attribute__((ext_vector_type(4)));
   __shared__ double red[kDeltaWaves][2][16][16];
   const int J = 2 * g.B;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row0 = blockIdx.x * 16, col0 = blockIdx.y * 32;
-  const int kt = min(nu, row0 + 16);
+  const int kt = src_ptr[u0 + min(nu, row0 + 16)] - s0;
   const int chunk = ((kt + kDeltaWaves - 1) / kDeltaWaves + 3) & ~3;
   const int kb = wave * chunk, ke = min(kt, kb + chunk);
   const int r = row0 + (lane & 15), q = lane >> 4;
@@ -303,9 +293,11 @@ __global__ __launch_bounds__(64 * kDeltaWaves) void delta_apply_kernel(
     for (int t = 0; t < 4; ++t) {
       const int k = kbase + 4 * t + q;
       const bool kok = k < ke;
+      const int yr = kok ? src_yrow[s0 + k] : 0;
+      const double* yrow = Y + (int64_t)(yr >> 1) * g.ncols + ((yr & 1) ? J : 0);
       pa[t] = (rok && kok) ? Minv[(int64_t)k * ld + r] : 0.0;
-      pb0[t] = (c0ok && kok) ? beta[(int64_t)k * J + c0] : 0.0;
-      pb1[t] = (c1ok && kok) ? beta[(int64_t)k * J + c1] : 0.0;
+      pb0[t] = (c0ok && kok) ? yrow[c0] : 0.0;
+      pb1[t] = (c1ok && kok) ? yrow[c1] : 0.0;
     }
   };
   auto mfma4 = [&](const double* pa, const double* pb0, const double* pb1) {
@@ -332,8 +324,8 @@ __global__ __launch_bounds__(64 * kDeltaWaves) void delta_apply_kernel(
     red[wave][1][q + 4 * v][lane & 15] = acc1[v];
   }
   __syncthreads();
-  if (threadIdx.x < 512) {
-    const int ct = threadIdx.x >> 8, i = (threadIdx.x >> 4) & 15, c = threadIdx.x & 15;
+  for (int e = threadIdx.x; e < 512; e += 64 * kDeltaWaves) {
+    const int ct = e >> 8, i = (e >> 4) & 15, c = e & 15;
     double sum = 0.0;
 #pragma unroll
     for (int w = 0; w < kDeltaWaves; ++w) sum += red[w][ct][i][c];
@@ -504,10 +496,11 @@ void build_delta_inverses(Plan& p) {
   fb.minv_ld.assign(nblk, 0);
   int64_t tot = 0;
   for (int blk = 0; blk < nblk; ++blk) {
-    const int nu = fb.unk_ptr[blk + 1] - fb.unk_ptr[blk];
+    const int u0 = fb.unk_ptr[blk], nu = fb.unk_ptr[blk + 1] - u0;
+    const int ns = fb.src_ptr[u0 + nu] - fb.src_ptr[u0];
     fb.minv_ld[blk] = (int32_t)round_up(std::max(nu, 1), 16);
     fb.minv_off[blk] = tot;
-    tot += (int64_t)fb.minv_ld[blk] * nu;
+    tot += (int64_t)fb.minv_ld[blk] * ns;
   }
   fb.minv_off[nblk] = tot;
   fb.d_minv.alloc(sizeof(double) * (size_t)std::max<int64_t>(tot, 1));
@@ -530,12 +523,23 @@ void build_delta_inverses(Plan& p) {
         for (int q = 0; q <= c; ++q) row[q] -= x * rc[q];
       }
     }
-    Mt.assign((size_t)ld * nu, 0.0);
-    for (int ul = 0; ul < nu; ++ul)
-      for (int q = 0; q <= ul; ++q) Mt[(size_t)q * ld + ul] = Mr[(size_t)ul * nu + q];
+    // column s (a source of unknown c) holds column c of M: rows ul >= c
+    const int sb = fb.src_ptr[u0], ns = fb.src_ptr[u0 + nu] - sb;
+    Mt.assign((size_t)ld * ns, 0.0);
+    for (int c = 0; c < nu; ++c)
+      for (int sg = fb.src_ptr[u0 + c]; sg < fb.src_ptr[u0 + c + 1]; ++sg)
+        for (int ul = c; ul < nu; ++ul) Mt[(size_t)(sg - sb) * ld + ul] = Mr[(size_t)ul * nu + c];
     OSHT_HIP(hipMemcpy(fb.d_minv.as<double>() + fb.minv_off[blk], Mt.data(), sizeof(double) * Mt.size(),
                        hipMemcpyHostToDevice));
   }
+  // per source: 2 (slot L + alias row) + (order < 0 on spin 0)
+  std::vector<int32_t> yrow(fb.src_slot.size());
+  for (size_t i = 0; i < yrow.size(); ++i) {
+    const int64_t row = (int64_t)fb.src_slot[i] * p.L + fb.src_row[i];
+    OSHT_CHECK(row < (int64_t)1 << 30, OSHT_ENOTSUP, "alias row index out of range");
+    yrow[i] = (int32_t)(2 * row + ((p.spin == 0 && fb.src_m[i] < 0) ? 1 : 0));
+  }
+  put_vec(fb.d_src_yrow, yrow);
 }
 
 }  // namespace
@@ -743,14 +747,11 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
       if (fb.dense) {
         ProfScope ps(p.prof, "delta_solve", st);
         const int J = 2 * (int)B;
-        hipLaunchKernelGGL(delta_beta_kernel, dim3((unsigned)ceil_div((int64_t)nu * J, 256)), dim3(256), 0, st, g, u0,
-                           nu, fb.d_src_ptr.as<int32_t>(), fb.d_src_slot.as<int32_t>(), fb.d_src_row.as<int32_t>(),
-                           fb.d_src_m.as<int32_t>(), p.w_Y.as<double>(), p.w_beta.as<double>());
-        OSHT_HIP(hipGetLastError());
         hipLaunchKernelGGL(delta_apply_kernel, dim3((unsigned)ceil_div(nu, 16), (unsigned)ceil_div(J, 32)),
-                           dim3(64 * kDeltaWaves), 0, st, g, u0, nu, fb.d_minv.as<double>() + fb.minv_off[blk],
-                           fb.minv_ld[blk], p.w_beta.as<double>(), fb.d_unk_slot.as<int32_t>(),
-                           fb.d_unk_r.as<int32_t>(), fb.d_unk_m.as<int32_t>(), p.w_D.as<double>(), bD);
+                           dim3(64 * kDeltaWaves), 0, st, g, u0, nu, fb.src_ptr[u0], fb.d_src_ptr.as<int32_t>(),
+                           fb.d_src_yrow.as<int32_t>(), fb.d_minv.as<double>() + fb.minv_off[blk], fb.minv_ld[blk],
+                           p.w_Y.as<double>(), fb.d_unk_slot.as<int32_t>(), fb.d_unk_r.as<int32_t>(),
+                           fb.d_unk_m.as<int32_t>(), p.w_D.as<double>(), bD);
         OSHT_HIP(hipGetLastError());
       } else {
         ProfScope ps(p.prof, "delta_solve", st);
@@ -860,7 +861,6 @@ void tune_forward_blocks(Plan& p) {
   p.w_Y.release();
   p.w_H.release();
   p.w_D.release();
-  p.w_beta.release();
 }
 
 void run_forward_adjoint_blocked(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st) {

@@ -195,13 +195,11 @@ void ensure_workspace(Plan& p, int64_t B) {
   const size_t xy = sizeof(double) * (size_t)p.nslots * p.L * ncols;
   const size_t hb = sizeof(double) * 2 * (size_t)p.L * p.L * B;
   const size_t db = sizeof(double) * (size_t)p.nslots * std::max(p.fb.b, 1) * ncols;
-  const size_t bb = sizeof(double) * (size_t)std::max(p.fb.max_unk, 1) * 2 * B;
-  const bool grow = (xy > p.w_X.bytes) || (hb > p.w_H.bytes) || (db > p.w_D.bytes) || (bb > p.w_beta.bytes);
+  const bool grow = (xy > p.w_X.bytes) || (hb > p.w_H.bytes) || (db > p.w_D.bytes);
   p.w_X.reserve(xy);
   p.w_Y.reserve(xy);
   p.w_H.reserve(hb);
   p.w_D.reserve(db);
-  p.w_beta.reserve(bb);
   if (!grow && p.ws_batch == B && !p.h_gdesc.empty()) return;
   // descriptor tables are rewritten below: earlier work on any stream may
   // still read them
