@@ -105,3 +105,40 @@ def test_batch_rejects_mixed_batch_sizes_on_one_plan():
     d = torch.zeros((1, 256), dtype=torch.complex128, device="cuda")
     with pytest.raises(OshtError):
         batch_run([(p, "inverse", a, b), (p, "inverse", c, d)])
+
+
+def test_graph_replays_match_eager_after_eager_work():
+    """One captured graph (inverse and forward jobs of two plans, one of them
+    spin 2) replayed four times, with eager transforms of the same batch
+    shapes on the same plans and host synchronizations between replays:
+    the graph is replayed, not captured again (its handle is unchanged; a
+    new capture is allocated before the old graph is freed), and every replay
+    equals the eager results bit for bit."""
+    import torch
+    from paper_1403_4661_amd import BatchGraph, Plan, batch_run
+
+    pa, pb = Plan(64, 0, precision="fp32-fwd"), Plan(40, 2, precision="fp32-fwd")
+    fa_in = to_dev(inputs.coeffs(64, 3, seed=21))
+    fb_in = to_dev(inputs.coeffs(40, 2, seed=22, spin=2))
+    sa = to_dev(inputs.samples_uniform(64, 3, seed=23))
+    eager = {"ia": pa.inverse(fa_in), "fa": pa.forward(sa), "ib": pb.inverse(fb_in)}
+    ref = {k: to_host(v) for k, v in eager.items()}
+    out = {k: torch.empty_like(v) for k, v in eager.items()}
+    jobs = [(pa, "inverse", fa_in, out["ia"]), (pa, "forward", sa, out["fa"]), (pb, "inverse", fb_in, out["ib"])]
+    g = BatchGraph()
+    batch_run(jobs, g)
+    handle = g._h.value
+    for k in ref:
+        assert np.array_equal(to_host(out[k]), ref[k]), k
+    for rep in range(4):
+        # eager work of the same shapes on the same plans (no workspace rebuild)
+        pa.inverse(to_dev(inputs.coeffs(64, 3, seed=30 + rep)))
+        pa.forward(to_dev(inputs.samples_uniform(64, 3, seed=40 + rep)))
+        pb.inverse(to_dev(inputs.coeffs(40, 2, seed=50 + rep, spin=2)))
+        torch.cuda.synchronize()
+        for v in out.values():
+            v.zero_()
+        batch_run(jobs, g)
+        assert g._h.value == handle, rep
+        for k in ref:
+            assert np.array_equal(to_host(out[k]), ref[k]), (rep, k)
