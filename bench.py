@@ -27,7 +27,9 @@ Prints one JSON line with, in addition:
                 instrumented dispatch, so the events are taken over a second
                 pass of the same K steps right after the timed one, and
                 `value` / `ms_per_step` come from the uninstrumented pass
-                (`ms_per_step_instrumented` reports the second);
+                (`ms_per_step_instrumented` reports the second;
+                `ms_per_step_graph_replay_median`, the median of 20 replays
+                of the step captured into one HIP graph);
   cpu_baseline  the FP64 CPU oracle (tests' reference implementation) timed on
                 the host on a bounded sample (see 'sample'), scaled to the
                 metric's unit.
@@ -198,8 +200,25 @@ def run_path(name, plan, flm, steps, warmup):
     dt_ins = time.perf_counter() - t1
     n, ms = plan.kernel_time("apply_forward")
     plan.set_profiling(False)
+    # the same step captured once into a HIP graph (osht_batch_run) and
+    # replayed: median of 20 replays, each timed by events on the stream
+    from paper_1403_4661_amd import BatchGraph, batch_run
+    graph = BatchGraph()
+    jobs = [(plan, "inverse", flm, f), (plan, "forward", f, g)]
+    batch_run(jobs, graph)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = []
+    for _ in range(20):
+        e0.record()
+        batch_run(jobs, graph)
+        e1.record()
+        e1.synchronize()
+        reps.append(e0.elapsed_time(e1))
+    graph.close()
+    reps.sort()
     return {"seconds": dt, "seconds_instrumented": dt_ins, "f": f, "g": g, "apply_forward_launches": n,
-            "apply_forward_ms": ms}
+            "apply_forward_ms": ms, "graph_ms_median": 0.5 * (reps[9] + reps[10])}
 
 
 def main():
@@ -254,6 +273,7 @@ def main():
             "sht_per_s": B * args.steps / r["seconds"],
             "ms_per_step": ms_step,
             "ms_per_step_instrumented": r["seconds_instrumented"] / args.steps * 1e3,
+            "ms_per_step_graph_replay_median": r["graph_ms_median"],
             "max_rel_err_roundtrip": rel(r["g"], flm),
             "device_bytes": r["device_bytes"],
             "apply_forward": {"launches": r["apply_forward_launches"], "ms_total": r["apply_forward_ms"],
