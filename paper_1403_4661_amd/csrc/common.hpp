@@ -94,6 +94,8 @@ struct GemmDesc {
   double alpha, beta;
   int32_t m_lo;   // rows [m_lo, M) are computed and stored (tiles start at m_lo / 64)
   int32_t b32;    // B is float (else double); GemmRole::ApplyInverse32 only
+  int32_t c32;    // C is stored as float (beta must be 0); GemmRole::ApplyInverse32 only
+  int32_t pad;
 };
 
 struct GemmTask {

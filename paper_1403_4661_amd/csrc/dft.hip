@@ -322,7 +322,9 @@ __global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void ring_analysis_kernel(c
 // vector.  When the ring has fewer outputs than threads, each bin's order
 // list is split into C contiguous chunks whose partial sums are added in
 // chunk order (fixed summation order, deterministic).
-__global__ __launch_bounds__(256) void fold_kernel(const double* __restrict__ Y, cplx* __restrict__ H, int L, int B,
+// YT: double, or float for the FP32 inverse apply's output.
+template <class YT>
+__global__ __launch_bounds__(256) void fold_kernel(const YT* __restrict__ Y, cplx* __restrict__ H, int L, int B,
                                                    int spin0, int ncols) {
   __shared__ cplx part[256];
   const int k = blockIdx.x, n = 2 * k + 1;
@@ -341,9 +343,9 @@ __global__ __launch_bounds__(256) void fold_kernel(const double* __restrict__ Y,
       int slot, col;
       if (spin0) { slot = m < 0 ? -m : m; col = (m < 0 ? 2 * B : 0) + 2 * b; }
       else { slot = m + L - 1; col = 2 * b; }
-      const double2 y = *reinterpret_cast<const double2*>(Y + ((int64_t)slot * L + k) * ncols + col);
-      h.x += y.x;
-      h.y += y.y;
+      const YT* yp = Y + ((int64_t)slot * L + k) * ncols + col;
+      h.x += (double)yp[0];
+      h.y += (double)yp[1];
     }
     if (C == 1) H[(base + q) * B + b] = h;
     else part[u] = h;
@@ -530,8 +532,13 @@ void launch_ring_analysis(const Plan& p, const double* f, double* H, int64_t B, 
 }
 
 void launch_fold(const Plan& p, const double* Y, double* H, int64_t B, hipStream_t st) {
-  hipLaunchKernelGGL(fold_kernel, dim3(p.L), dim3(256), 0, st, Y, reinterpret_cast<cplx*>(H), p.L, (int)B,
-                     p.spin == 0 ? 1 : 0, p.ncols_per_map * (int)B);
+  // FP32 plans: the inverse apply wrote its output in FP32
+  if (p.fp32)
+    hipLaunchKernelGGL(fold_kernel<float>, dim3(p.L), dim3(256), 0, st, reinterpret_cast<const float*>(Y),
+                       reinterpret_cast<cplx*>(H), p.L, (int)B, p.spin == 0 ? 1 : 0, p.ncols_per_map * (int)B);
+  else
+    hipLaunchKernelGGL(fold_kernel<double>, dim3(p.L), dim3(256), 0, st, Y, reinterpret_cast<cplx*>(H), p.L, (int)B,
+                       p.spin == 0 ? 1 : 0, p.ncols_per_map * (int)B);
   OSHT_HIP(hipGetLastError());
 }
 

@@ -358,7 +358,14 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
       const int r = m0 + wave * 16 + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
       const int col = n0 + nb * 16 + (lane & 15);
       if (r >= d.m_lo && r < d.M && col < d.N) {
-        double* cp = d.C + (int64_t)r * d.sCr + (int64_t)col * d.sCc;
+        const int64_t ci = (int64_t)r * d.sCr + (int64_t)col * d.sCc;
+        if constexpr (std::is_same<TB, float>::value) {  // FP32 inverse apply: C may be FP32
+          if (d.c32) {
+            reinterpret_cast<float*>(d.C)[ci] = (float)(d.alpha * acc[nb][v]);
+            continue;
+          }
+        }
+        double* cp = d.C + ci;
         double x = d.alpha * acc[nb][v];
         if (d.beta != 0.0) x += d.beta * (PREFC ? cpre[nb][v] : *cp);
         *cp = x;

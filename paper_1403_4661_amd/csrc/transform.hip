@@ -245,9 +245,11 @@ void ensure_workspace(Plan& p, int64_t B) {
       };
       if (dir == kInv) {
         setA(f32, true, sl.offA); d.sAr = 1; d.sAc = sl.ldA; d.M = p.L; d.K = sl.K;
-        if (f32) {  // right-hand side written as FP32 into the same workspace
+        if (f32) {  // right-hand side and output in FP32, in the same workspaces
           d.B = reinterpret_cast<const double*>(reinterpret_cast<const float*>(X) + (int64_t)i * p.L * ncols);
           d.b32 = 1;
+          d.C = reinterpret_cast<double*>(reinterpret_cast<float*>(Y) + (int64_t)i * p.L * ncols);
+          d.c32 = 1;
         }
       }
       if (dir == kIadj) { setA(f32, true, sl.offA); d.sAr = sl.ldA; d.sAc = 1; d.M = sl.K; d.K = p.L; }
