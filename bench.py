@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--tune", action="store_true",
                     help="autotune the forward block shape at plan time (default: the built-in shape, which is "
                          "what the tuner picks for L=1024 on MI355X)")
+    ap.add_argument("--uneven", action="store_true",
+                    help="time the batch scheduler on 64 maps of uneven L and spin instead (one JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (HBM counter calibration)")
     return ap.parse_args()
@@ -221,10 +223,80 @@ def run_path(name, plan, flm, steps, warmup):
             "apply_forward_ms": ms, "graph_ms_median": 0.5 * (reps[9] + reps[10])}
 
 
+def run_uneven(args):
+    """The batch scheduler on the uneven workload: 64 maps, L drawn from
+    {64, 128, 256, 512} and spin from {0, 2, -2} (seed 2), flm ~ N(0,1)
+    zeroed for l < |s|, on OSHT_PREC_FP32_FWD plans, one job per (L, s)
+    group with its maps contiguous: an inverse per group and a forward per
+    spin-0 group (of the inverse's output).  The same job list is timed
+    three ways: issued job by job on one stream, through osht_batch_run
+    (plan groups on concurrent streams), and as a replayed HIP graph
+    (median of 20 replays, events on the stream)."""
+    import numpy as np
+    import torch
+
+    from paper_1403_4661_amd import BatchGraph, Plan, batch_run
+    from tests import inputs
+
+    torch.cuda.set_device(0)
+    Ls, ss, maps = inputs.uneven_batch(64, seed=2)
+    groups = {}
+    for i, key in enumerate(zip(Ls, ss)):
+        groups.setdefault(key, []).append(i)
+    keys = sorted(groups)
+    plans = {k: Plan(k[0], k[1], precision="fp32-fwd") for k in keys}
+    flm = {k: torch.as_tensor(np.stack([maps[i] for i in groups[k]])).cuda() for k in keys}
+    f = {k: torch.empty_like(flm[k]) for k in keys}
+    g = {k: torch.empty_like(flm[k]) for k in keys if k[1] == 0}
+    jobs = [(plans[k], "inverse", flm[k], f[k]) for k in keys]
+    jobs += [(plans[k], "forward", f[k], g[k]) for k in keys if k[1] == 0]
+
+    def eager():
+        for plan, direction, x, y in jobs:
+            getattr(plan, direction)(x, out=y)
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    for _ in range(2):
+        eager()
+        batch_run(jobs)
+    t_eager = timed(eager, args.steps)
+    t_batch = timed(lambda: batch_run(jobs), args.steps)
+    graph = BatchGraph()
+    batch_run(jobs, graph)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = []
+    for _ in range(20):
+        e0.record()
+        batch_run(jobs, graph)
+        e1.record()
+        e1.synchronize()
+        reps.append(e0.elapsed_time(e1))
+    graph.close()
+    reps.sort()
+    t_graph = 0.5 * (reps[9] + reps[10])
+    nmaps = sum(len(v) for v in groups.values())
+    print(json.dumps({
+        "metric": "uneven batch: 64 maps, L in {64,128,256,512}, s in {0,+-2}; inverse of all, forward of spin 0",
+        "value": nmaps / (t_graph * 1e-3), "unit": "maps/s (graph replay)", "n_gpus": 1, "steps": args.steps,
+        "ms_eager_job_by_job": t_eager, "ms_batch_run_streams": t_batch, "ms_graph_replay_median": t_graph,
+        "plans": len(keys), "jobs": len(jobs), "precision": "fp32-fwd", "data": "synthetic"}), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.uneven:
+        run_uneven(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: the transforms run on a single device; --gpus must be 1"}))
