@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--tune", action="store_true",
                     help="autotune the forward block shape at plan time (default: the built-in shape, which is "
                          "what the tuner picks for L=1024 on MI355X)")
+    ap.add_argument("--real", action="store_true",
+                    help="time real-map transforms (2x --batch real maps per step) instead (one JSON line)")
     ap.add_argument("--uneven", action="store_true",
                     help="time the batch scheduler on 64 maps of uneven L and spin instead (one JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -290,8 +292,55 @@ def run_uneven(args):
         "plans": len(keys), "jobs": len(jobs), "precision": "fp32-fwd", "data": "synthetic"}), flush=True)
 
 
+def run_real(args):
+    """Real maps, spin 0: one step = inverse_real then forward_real of
+    2 x batch real maps (two per complex transform), weighted symmetric
+    coefficients from seed 5, on the mixed and FP64 plans.  The same
+    uninstrumented timing as the complex paths."""
+    import numpy as np
+    import torch
+
+    from paper_1403_4661_amd import Plan
+    from tests import inputs
+
+    torch.cuda.set_device(0)
+    L, nreal = args.L, 2 * args.batch
+    flm_h = inputs.coeffs(L, nreal, seed=5, weighted=True)
+    sym = np.empty_like(flm_h)
+    for l in range(L):
+        m = np.arange(-l, l + 1)
+        sym[:, l * l + l + m] = ((-1.0) ** np.abs(m)) * np.conj(flm_h[:, l * l + l - m])
+    flm = torch.as_tensor(0.5 * (flm_h + sym)).cuda()
+    out = {}
+    for name in ("mixed", "fp64"):
+        plan = Plan(L, 0, precision=PRECISION[name])
+        f = torch.empty(flm.shape, dtype=torch.float64, device=flm.device)
+        g = torch.empty_like(flm)
+        for _ in range(args.warmup):
+            plan.inverse_real(flm, out=f)
+            plan.forward_real(f, out=g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.inverse_real(flm, out=f)
+            plan.forward_real(f, out=g)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        out[name] = {"real_maps_per_s": nreal / dt, "ms_per_step": dt * 1e3,
+                     "max_rel_err_roundtrip": float((g - flm).abs().max() / flm.abs().max())}
+        del plan
+        torch.cuda.empty_cache()
+    print(json.dumps({
+        "metric": f"fwd+inv real-map SHT/s at L={L}, {nreal} real maps (two per complex transform)",
+        "value": out["mixed"]["real_maps_per_s"], "unit": "real maps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "paths": out, "data": "synthetic"}), flush=True)
+
+
 def main():
     args = parse()
+    if args.real:
+        run_real(args)
+        return
     if args.calibrate_copy:
         calibrate_copy()
         return

@@ -141,7 +141,29 @@ int osht_forward(const osht_plan_t* plan, const void* f, void* flm, int64_t batc
                  hipStream_t stream);
 
 /*
- * Adjoints: exact conjugate transposes of the two maps above with respect to
+ * Real maps (spin 0 only; other plans return OSHT_ENOTSUP).  A map with real
+ * samples has coefficients with f_{l,-m} = (-1)^m conj(f_{l,m}) (the
+ * harmonics' conjugation rule, Eq. yellm:conj of the appendix on spherical
+ * harmonics); two such maps are carried by one complex transform, so a batch
+ * of real maps costs half as many complex transforms.
+ *   osht_forward_real: f device, batch * L*L float64 (read) ->
+ *     flm device, batch * L*L complex128, the full layout including m < 0
+ *     (written).  Equals osht_forward of the same samples.
+ *   osht_inverse_real: flm device, batch * L*L complex128 (read) ->
+ *     f device, batch * L*L float64 (written): the real part of
+ *     osht_inverse(flm), which is the whole of it when flm has the symmetry
+ *     above.
+ * In and out must not overlap.  Asynchronous on stream, except that a call
+ * whose batch needs larger packing buffers synchronizes the device to grow
+ * them.  Not accepted by osht_batch_run.
+ */
+int osht_forward_real(const osht_plan_t* plan, const void* f, void* flm, int64_t batch,
+                      hipStream_t stream);
+int osht_inverse_real(const osht_plan_t* plan, const void* flm, void* f, int64_t batch,
+                      hipStream_t stream);
+
+/*
+ * Adjoints: exact conjugate transposes of osht_inverse and osht_forward with respect to
  * the Euclidean inner product on C^{L^2} (samples and coefficients alike).
  *   inverse_adjoint: f_bar (samples)     -> flm_bar (coefficients)
  *   forward_adjoint: flm_bar (coefficients) -> f_bar (samples)

@@ -114,6 +114,40 @@ class Plan:
                                       xb.shape[0], ctypes.c_void_p(stream)))
         return y.reshape(-1) if squeeze else y
 
+    def _run_real(self, fn, x, in_dtype, out_dtype, out=None):
+        import torch
+
+        if not isinstance(x, torch.Tensor) or x.dtype != in_dtype:
+            raise TypeError(f"expected a {in_dtype} torch tensor")
+        if x.device != self.device:
+            raise ValueError(f"tensor on {x.device}, plan on {self.device}")
+        if self.spin != 0:
+            raise ValueError("real-map transforms are defined for spin 0 only")
+        squeeze = x.dim() == 1
+        xb = x.reshape(1, -1) if squeeze else x
+        if xb.dim() != 2 or xb.shape[1] != self.L * self.L:
+            raise ValueError(f"expected shape (B, {self.L * self.L})")
+        xb = xb.contiguous()
+        y = torch.empty(xb.shape, dtype=out_dtype, device=self.device) if out is None else out
+        if y.shape != xb.shape or y.dtype != out_dtype or not y.is_contiguous() or y.device != self.device:
+            raise ValueError("bad output tensor")
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(getattr(lib(), fn)(self._h, ctypes.c_void_p(xb.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                      xb.shape[0], ctypes.c_void_p(stream)))
+        return y.reshape(-1) if squeeze else y
+
+    def forward_real(self, f, out=None):
+        """Coefficients (complex128, full layout) of real maps (float64
+        samples); two maps per complex transform.  Spin 0."""
+        import torch
+        return self._run_real("osht_forward_real", f, torch.float64, torch.complex128, out)
+
+    def inverse_real(self, flm, out=None):
+        """Real samples (float64): the real part of the inverse, exact for
+        coefficients with f_{l,-m} = (-1)^m conj(f_lm).  Spin 0."""
+        import torch
+        return self._run_real("osht_inverse_real", flm, torch.complex128, torch.float64, out)
+
     def inverse(self, flm, out=None):
         """Samples from coefficients (Procedure 2)."""
         return self._run("osht_inverse", flm, out)

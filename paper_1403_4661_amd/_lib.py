@@ -37,6 +37,8 @@ EXPORTED = (
     "osht_forward",
     "osht_inverse_adjoint",
     "osht_forward_adjoint",
+    "osht_forward_real",
+    "osht_inverse_real",
     "osht_strerror",
     "osht_last_error_message",
     "osht_plan_set_profiling",
@@ -106,7 +108,8 @@ def lib():
     L.osht_plan_destroy.argtypes = [vp]
     L.osht_plan_info.argtypes = [vp, ctypes.POINTER(OshtInfo)]
     L.osht_plan_theta.argtypes = [vp, i32p]
-    for name in ("osht_inverse", "osht_forward", "osht_inverse_adjoint", "osht_forward_adjoint"):
+    for name in ("osht_inverse", "osht_forward", "osht_inverse_adjoint", "osht_forward_adjoint", "osht_forward_real",
+                 "osht_inverse_real"):
         fn = getattr(L, name)
         fn.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
         fn.restype = ctypes.c_int

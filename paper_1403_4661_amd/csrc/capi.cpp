@@ -110,6 +110,33 @@ int run_transform(const osht_plan_t* plan, const void* in, void* out, int64_t ba
   return OSHT_OK;
 }
 
+// As run_transform, with one side real (float64) and the other complex128.
+template <class Fn>
+int run_real_transform(const osht_plan_t* plan, const void* in, int64_t bin, bool in_cplx, void* out, int64_t bout,
+                       bool out_cplx, Fn fn) {
+  if (!plan) return fail(OSHT_EINVAL, "plan is NULL");
+  if (!in || !out) return fail(OSHT_EINVAL, "input or output pointer is NULL");
+  if (bin < 1 || bin > 65535) return fail(OSHT_EINVAL, "batch must be in [1, 65535]");
+  Plan& p = const_cast<osht_plan_t*>(plan)->p;
+  if (p.spin != 0) return fail(OSHT_ENOTSUP, "real-map transforms are defined for spin 0 only");
+  const size_t n = (size_t)p.L * p.L;
+  const size_t ib = sizeof(double) * n * (size_t)bin * (in_cplx ? 2 : 1);
+  const size_t ob = sizeof(double) * n * (size_t)bout * (out_cplx ? 2 : 1);
+  const char* x = static_cast<const char*>(in);
+  const char* y = static_cast<const char*>(out);
+  if (x < y + ob && y < x + ib) return fail(OSHT_EINVAL, "input and output buffers overlap");
+  try {
+    std::lock_guard<std::mutex> lk(p.mu);
+    DeviceGuard g(p.device);
+    fn(p, static_cast<const double*>(in), static_cast<double*>(out));
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(OSHT_ENOMEM, "host allocation failed");
+  }
+  return OSHT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -233,6 +260,16 @@ int osht_inverse(const osht_plan_t* plan, const void* flm, void* f, int64_t batc
 int osht_forward(const osht_plan_t* plan, const void* f, void* flm, int64_t batch, hipStream_t stream) {
   return run_transform(plan, f, flm, batch,
                        [&](Plan& p, const double* a, double* b) { osht::run_forward(p, a, b, batch, stream); });
+}
+
+int osht_forward_real(const osht_plan_t* plan, const void* f, void* flm, int64_t batch, hipStream_t stream) {
+  return run_real_transform(plan, f, batch, false, flm, batch, true,
+                            [&](Plan& p, const double* a, double* b) { osht::run_forward_real(p, a, b, batch, stream); });
+}
+
+int osht_inverse_real(const osht_plan_t* plan, const void* flm, void* f, int64_t batch, hipStream_t stream) {
+  return run_real_transform(plan, flm, batch, true, f, batch, false,
+                            [&](Plan& p, const double* a, double* b) { osht::run_inverse_real(p, a, b, batch, stream); });
 }
 
 int osht_inverse_adjoint(const osht_plan_t* plan, const void* f_bar, void* flm_bar, int64_t batch, hipStream_t stream) {

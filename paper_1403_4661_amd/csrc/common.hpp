@@ -195,6 +195,7 @@ struct Plan {
   int max_logM = 0;
   // per-call workspace (grown on demand)
   DevBuf w_X, w_Y, w_H, w_T, w_D;
+  DevBuf w_R1, w_R2;          // packed complex maps of the real-map transforms
   FwdBlocks fb;
   std::vector<int32_t> h_btask_ptr;   // per block: [fwd, corr, end) offsets into d_btask
   DevBuf d_btask;
@@ -238,6 +239,10 @@ void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t s
 void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st);
 void run_inverse_adjoint(Plan& p, const double* fbar, double* flmbar, int64_t B, hipStream_t st);
 void run_forward_adjoint(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st);
+// real maps, spin 0: f real [B][L^2] <-> flm complex [B][L^2] (two maps per
+// complex transform)
+void run_forward_real(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st);
+void run_inverse_real(Plan& p, const double* flm, double* f, int64_t B, hipStream_t st);
 // Sizes the workspace and descriptor tables for batch B (synchronous; must
 // precede any graph capture of the transforms).
 void prepare_transforms(Plan& p, int64_t B);

@@ -499,4 +499,127 @@ void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t s
   else run_forward_levels(p, f, flm, B, st);
 }
 
+// ---------------------------------------------------------------- real maps
+// Spin-0 maps with real samples have coefficients with the symmetry
+// f_{l,-m} = (-1)^m conj(f_{l,m}), from the harmonics' conjugation rule
+// (Eq. yellm:conj, appendix on spherical harmonics).  Two real maps a and b are transformed as the one complex map
+// z = a + i b: the inverse of z has real part a and imaginary part b, and
+// the forward of z gives a_lm = (z_lm + R(z)_lm)/2 and
+// b_lm = (z_lm - R(z)_lm)/(2i) with R(z)_lm = (-1)^m conj(z_{l,-m}).  Half
+// the right-hand-side columns, ring DFTs and matrix work per real map.
+
+namespace {
+
+__device__ __forceinline__ void lm_of(int64_t i, int& l, int& m) {
+  l = (int)sqrt((double)i);
+  while ((int64_t)l * l > i) --l;
+  while ((int64_t)(l + 1) * (l + 1) <= i) ++l;
+  m = (int)(i - (int64_t)l * l - l);
+}
+
+// R(x)_lm = (-1)^m conj(x_{l,-m}) of one map's coefficients
+__device__ __forceinline__ double2 reflect(const double2* __restrict__ x, int64_t i, int l, int m) {
+  const double2 v = x[(int64_t)l * l + l - m];
+  return (m & 1) ? make_double2(-v.x, v.y) : make_double2(v.x, -v.y);
+}
+
+// z[j] = f[2j] + i f[2j+1] (f[2j+1] = 0 past the batch)
+__global__ void pack_real_kernel(const double* __restrict__ f, double2* __restrict__ z, int64_t n, int64_t B,
+                                 int64_t Bc) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Bc * n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / n, i = e - j * n;
+    const double a = f[2 * j * n + i];
+    const double b = 2 * j + 1 < B ? f[(2 * j + 1) * n + i] : 0.0;
+    z[e] = make_double2(a, b);
+  }
+}
+
+// f[2j] = Re z[j], f[2j+1] = Im z[j]
+__global__ void unpack_real_kernel(const double2* __restrict__ z, double* __restrict__ f, int64_t n, int64_t B,
+                                   int64_t Bc) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Bc * n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / n, i = e - j * n;
+    const double2 v = z[e];
+    f[2 * j * n + i] = v.x;
+    if (2 * j + 1 < B) f[(2 * j + 1) * n + i] = v.y;
+  }
+}
+
+// zlm[j] = S(flm[2j]) + i S(flm[2j+1]), S(x) = (x + R(x))/2: the inverse of
+// S(x) is the real part of the inverse of x, so any input is accepted
+__global__ void pack_coef_kernel(const double2* __restrict__ flm, double2* __restrict__ z, int64_t n, int64_t B,
+                                 int64_t Bc) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Bc * n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / n, i = e - j * n;
+    int l, m;
+    lm_of(i, l, m);
+    const double2* a = flm + 2 * j * n;
+    const double2 av = a[i], ar = reflect(a, i, l, m);
+    double2 s = make_double2(0.5 * (av.x + ar.x), 0.5 * (av.y + ar.y));
+    if (2 * j + 1 < B) {
+      const double2* b = flm + (2 * j + 1) * n;
+      const double2 bv = b[i], br = reflect(b, i, l, m);
+      const double2 t = make_double2(0.5 * (bv.x + br.x), 0.5 * (bv.y + br.y));
+      s.x -= t.y;  // + i t
+      s.y += t.x;
+    }
+    z[e] = s;
+  }
+}
+
+// flm[2j] = (z + R(z))/2, flm[2j+1] = (z - R(z))/(2i)
+__global__ void unpack_coef_kernel(const double2* __restrict__ z, double2* __restrict__ flm, int64_t n, int64_t B,
+                                   int64_t Bc) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Bc * n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / n, i = e - j * n;
+    int l, m;
+    lm_of(i, l, m);
+    const double2* zj = z + j * n;
+    const double2 v = zj[i], r = reflect(zj, i, l, m);
+    flm[2 * j * n + i] = make_double2(0.5 * (v.x + r.x), 0.5 * (v.y + r.y));
+    if (2 * j + 1 < B) {
+      const double dx = 0.5 * (v.x - r.x), dy = 0.5 * (v.y - r.y);
+      flm[(2 * j + 1) * n + i] = make_double2(dy, -dx);  // (dx + i dy) / i
+    }
+  }
+}
+
+dim3 elementwise_grid(int64_t n) { return dim3((unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(n, 256), 1), 8192)); }
+
+void real_workspace(Plan& p, int64_t Bc) {
+  OSHT_CHECK(p.spin == 0, OSHT_ENOTSUP, "real-map transforms are defined for spin 0 only");
+  const size_t bytes = sizeof(double) * 2 * (size_t)p.L * p.L * (size_t)Bc;
+  if (bytes > p.w_R1.bytes || bytes > p.w_R2.bytes) OSHT_HIP(hipDeviceSynchronize());
+  p.w_R1.reserve(bytes);
+  p.w_R2.reserve(bytes);
+}
+
+}  // namespace
+
+void run_forward_real(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {
+  const int64_t Bc = (B + 1) / 2, n = (int64_t)p.L * p.L;
+  real_workspace(p, Bc);
+  double2* z = p.w_R1.as<double2>();
+  double2* zlm = p.w_R2.as<double2>();
+  hipLaunchKernelGGL(pack_real_kernel, elementwise_grid(Bc * n), dim3(256), 0, st, f, z, n, B, Bc);
+  OSHT_HIP(hipGetLastError());
+  run_forward(p, reinterpret_cast<const double*>(z), reinterpret_cast<double*>(zlm), Bc, st);
+  hipLaunchKernelGGL(unpack_coef_kernel, elementwise_grid(Bc * n), dim3(256), 0, st, zlm,
+                     reinterpret_cast<double2*>(flm), n, B, Bc);
+  OSHT_HIP(hipGetLastError());
+}
+
+void run_inverse_real(Plan& p, const double* flm, double* f, int64_t B, hipStream_t st) {
+  const int64_t Bc = (B + 1) / 2, n = (int64_t)p.L * p.L;
+  real_workspace(p, Bc);
+  double2* zlm = p.w_R1.as<double2>();
+  double2* z = p.w_R2.as<double2>();
+  hipLaunchKernelGGL(pack_coef_kernel, elementwise_grid(Bc * n), dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(flm), zlm, n, B, Bc);
+  OSHT_HIP(hipGetLastError());
+  run_inverse(p, reinterpret_cast<const double*>(zlm), reinterpret_cast<double*>(z), Bc, st);
+  hipLaunchKernelGGL(unpack_real_kernel, elementwise_grid(Bc * n), dim3(256), 0, st, z, f, n, B, Bc);
+  OSHT_HIP(hipGetLastError());
+}
+
 }  // namespace osht
