@@ -195,7 +195,7 @@ struct Plan {
   int max_logM = 0;
   // per-call workspace (grown on demand)
   DevBuf w_X, w_Y, w_H, w_T, w_D;
-  DevBuf w_R1, w_R2;          // packed complex maps of the real-map transforms
+  DevBuf w_R1;                // packed complex coefficients of the real-map transforms
   FwdBlocks fb;
   std::vector<int32_t> h_btask_ptr;   // per block: [fwd, corr, end) offsets into d_btask
   DevBuf d_btask;
@@ -235,8 +235,10 @@ struct ProfScope {
 // plan construction (plan.hip)
 void build_plan(Plan& p);
 // transforms (transform.hip)
-void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t st);
-void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st);
+// real_maps > 0: the samples f are real_maps real maps (float64), two per
+// complex map of the batch B = ceil(real_maps / 2)
+void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t st, int64_t real_maps = 0);
+void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st, int64_t real_maps = 0);
 void run_inverse_adjoint(Plan& p, const double* fbar, double* flmbar, int64_t B, hipStream_t st);
 void run_forward_adjoint(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st);
 // real maps, spin 0: f real [B][L^2] <-> flm complex [B][L^2] (two maps per
@@ -263,7 +265,7 @@ void build_chirps(Plan& p);
 // samples [b][L^2] -> bins [L^2][B] (normalised analysis, scale 1/n_k) or
 // unnormalised (scale 1)
 void launch_ring_analysis(const Plan& p, const double* f, double* H, int64_t B, bool normalise,
-                          hipStream_t st);
+                          hipStream_t st, int64_t real_maps = 0);
 
 // blocked forward sweep (sweep.hip)
 void build_fwd_blocks(Plan& p, int b);
@@ -273,7 +275,7 @@ bool fwd_blocks_fit(Plan& p, int b);
 // keeps the fastest; results cached per (device, L, spin, precision) in
 // Plan::cache_dir when set
 void tune_forward_blocks(Plan& p);
-void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st);
+void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st, int64_t real_maps = 0);
 void run_forward_adjoint_blocked(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st);
 
 // placement (theta.cpp)

@@ -280,24 +280,34 @@ __device__ __forceinline__ void bluestein(cplx* v, const FftCtx& cx, const cplx*
 }
 
 // samples f[b][L^2] -> bins H[(k^2 + q) * B + b] (scale 1/n or 1).
-template <int LOGM>
+template <int LOGM, bool REAL>
 __global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void ring_analysis_kernel(const RingDesc* __restrict__ rings, int k0,
                                                             int npairs, const cplx* __restrict__ chirp_fft,
                                                             const cplx* __restrict__ chirp_tab,
                                                             const cplx* __restrict__ tw, int logMmax, int L,
                                                             const cplx* __restrict__ f, cplx* __restrict__ H, int B,
-                                                            int normalise) {
+                                                            int normalise, const double* __restrict__ freal,
+                                                            int Breal) {
   constexpr int logM = LOGM, M = 1 << LOGM, T = M / RPT;
   const PairCtx pc = pair_of(rings, k0, npairs, B, T);
   const int t = threadIdx.x % T;
   FftCtx cx{lds_buf + (threadIdx.x / T) * (M + M / 16), tw, logM, logMmax, t, T};
   const cplx* w = chirp_tab + pc.base;
   const cplx* fr = f + (int64_t)pc.b * L * L + pc.base;
+  // REAL: complex map b carries the real maps 2b (real part) and 2b+1
+  const double* fa = freal + (int64_t)(2 * pc.b) * L * L + pc.base;
+  const double* fb = fa + (int64_t)L * L;
+  const bool has_b = 2 * pc.b + 1 < Breal;
   cplx v[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int p = t + i * T;
-    v[i] = (pc.active && p < pc.n) ? cmul(fr[p], w[p]) : cplx{0.0, 0.0};
+    cplx x = {0.0, 0.0};
+    if (pc.active && p < pc.n) {
+      if constexpr (REAL) x = cplx{fa[p], has_b ? fb[p] : 0.0};
+      else x = fr[p];
+    }
+    v[i] = (pc.active && p < pc.n) ? cmul(x, w[p]) : cplx{0.0, 0.0};
   }
   bluestein<LOGM>(v, cx, chirp_fft + pc.off, pc.active);
   if (pc.active) {
@@ -363,13 +373,14 @@ __global__ __launch_bounds__(256) void fold_kernel(const YT* __restrict__ Y, cpl
 
 // Synthesis of (ring, map) pairs from the map-fastest bins H (optionally
 // times 1/n): f[b][k^2 + j] = sum_q H_k[q] e^{+2 pi i q j / n}.
-template <int LOGM>
+template <int LOGM, bool REAL>
 __global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void ring_synthesis_kernel(const RingDesc* __restrict__ rings, int k0,
                                                              int npairs, const cplx* __restrict__ chirp_fft,
                                                              const cplx* __restrict__ chirp_tab,
                                                              const cplx* __restrict__ tw, int logMmax, int L,
                                                              const cplx* __restrict__ H, int scale_inv_n,
-                                                             cplx* __restrict__ f, int B) {
+                                                             cplx* __restrict__ f, int B, double* __restrict__ freal,
+                                                             int Breal) {
   constexpr int logM = LOGM, M = 1 << LOGM, T = M / RPT;
   const PairCtx pc = pair_of(rings, k0, npairs, B, T);
   const int t = threadIdx.x % T;
@@ -391,12 +402,21 @@ __global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void ring_synthesis_kernel(
   if (pc.active) {
     const double sc = 1.0 / M;
     cplx* fr = f + (int64_t)pc.b * L * L + pc.base;
+    // REAL: the real part is real map 2b, the imaginary part real map 2b+1
+    double* fa = freal + (int64_t)(2 * pc.b) * L * L + pc.base;
+    double* fb = fa + (int64_t)L * L;
+    const bool has_b = 2 * pc.b + 1 < Breal;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int j = t + i * T;
       if (j < pc.n) {
         const cplx c = cmul(v[i], w[j]);
-        fr[j] = {c.x * sc, -c.y * sc};
+        if constexpr (REAL) {
+          fa[j] = c.x * sc;
+          if (has_b) fb[j] = -c.y * sc;
+        } else {
+          fr[j] = {c.x * sc, -c.y * sc};
+        }
       }
     }
   }
@@ -515,18 +535,23 @@ void build_chirps(Plan& p) {
   });
 }
 
-void launch_ring_analysis(const Plan& p, const double* f, double* H, int64_t B, bool normalise, hipStream_t st) {
+void launch_ring_analysis(const Plan& p, const double* f, double* H, int64_t B, bool normalise, hipStream_t st,
+                          int64_t real_maps) {
   for_each_class(p, [&](int k0, int k1, int logM) {
     with_logM(logM, [&](auto lg) {
       constexpr int LG = decltype(lg)::value;
       const Shape sh = shape_for(LG);
-      allow_lds((const void*)ring_analysis_kernel<LG>, sh.lds);
       const int np = (k1 - k0) * (int)B;
-      hipLaunchKernelGGL(ring_analysis_kernel<LG>, dim3((unsigned)ceil_div(np, sh.F)), dim3(sh.nthr), sh.lds, st,
-                         p.d_rings.as<RingDesc>(), k0, np, p.d_chirp.as<cplx>(), p.d_chirp_tab.as<cplx>(),
-                         p.d_twiddle.as<cplx>(), p.max_logM, p.L, reinterpret_cast<const cplx*>(f),
-                         reinterpret_cast<cplx*>(H), (int)B, normalise ? 1 : 0);
-      OSHT_HIP(hipGetLastError());
+      auto go = [&](auto kernel) {
+        allow_lds((const void*)kernel, sh.lds);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)ceil_div(np, sh.F)), dim3(sh.nthr), sh.lds, st,
+                           p.d_rings.as<RingDesc>(), k0, np, p.d_chirp.as<cplx>(), p.d_chirp_tab.as<cplx>(),
+                           p.d_twiddle.as<cplx>(), p.max_logM, p.L, reinterpret_cast<const cplx*>(f),
+                           reinterpret_cast<cplx*>(H), (int)B, normalise ? 1 : 0, f, (int)real_maps);
+        OSHT_HIP(hipGetLastError());
+      };
+      if (real_maps > 0) go(ring_analysis_kernel<LG, true>);
+      else go(ring_analysis_kernel<LG, false>);
     });
   });
 }
@@ -542,18 +567,23 @@ void launch_fold(const Plan& p, const double* Y, double* H, int64_t B, hipStream
   OSHT_HIP(hipGetLastError());
 }
 
-void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, double* f, int64_t B, hipStream_t st) {
+void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, double* f, int64_t B, hipStream_t st,
+                           int64_t real_maps) {
   for_each_class(p, [&](int k0, int k1, int logM) {
     with_logM(logM, [&](auto lg) {
       constexpr int LG = decltype(lg)::value;
       const Shape sh = shape_for(LG);
-      allow_lds((const void*)ring_synthesis_kernel<LG>, sh.lds);
       const int np = (k1 - k0) * (int)B;
-      hipLaunchKernelGGL(ring_synthesis_kernel<LG>, dim3((unsigned)ceil_div(np, sh.F)), dim3(sh.nthr), sh.lds, st,
-                         p.d_rings.as<RingDesc>(), k0, np, p.d_chirp.as<cplx>(), p.d_chirp_tab.as<cplx>(),
-                         p.d_twiddle.as<cplx>(), p.max_logM, p.L, reinterpret_cast<const cplx*>(H), scale_inv_n,
-                         reinterpret_cast<cplx*>(f), (int)B);
-      OSHT_HIP(hipGetLastError());
+      auto go = [&](auto kernel) {
+        allow_lds((const void*)kernel, sh.lds);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)ceil_div(np, sh.F)), dim3(sh.nthr), sh.lds, st,
+                           p.d_rings.as<RingDesc>(), k0, np, p.d_chirp.as<cplx>(), p.d_chirp_tab.as<cplx>(),
+                           p.d_twiddle.as<cplx>(), p.max_logM, p.L, reinterpret_cast<const cplx*>(H), scale_inv_n,
+                           reinterpret_cast<cplx*>(f), (int)B, f, (int)real_maps);
+        OSHT_HIP(hipGetLastError());
+      };
+      if (real_maps > 0) go(ring_synthesis_kernel<LG, true>);
+      else go(ring_synthesis_kernel<LG, false>);
     });
   });
 }

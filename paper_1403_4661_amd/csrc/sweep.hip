@@ -29,7 +29,8 @@
 #include "xform.hpp"
 
 namespace osht {
-void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, double* f, int64_t B, hipStream_t st);
+void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, double* f, int64_t B, hipStream_t st,
+                           int64_t real_maps = 0);
 }
 
 namespace osht {
@@ -701,13 +702,13 @@ void build_fwd_blocks(Plan& p, int b) {
   }
 }
 
-void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {
+void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st, int64_t real_maps) {
   ensure_workspace(p, B);
   const Geo g = geo(p, B);
   const FwdBlocks& fb = p.fb;
   {
     ProfScope ps(p.prof, "ring_analysis", st);
-    launch_ring_analysis(p, f, p.w_H.as<double>(), B, true, st);
+    launch_ring_analysis(p, f, p.w_H.as<double>(), B, true, st, real_maps);
   }
   const int bD = std::max(fb.b, 1);
   const int64_t nD = (int64_t)p.nslots * bD * g.ncols;

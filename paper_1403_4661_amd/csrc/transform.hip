@@ -28,7 +28,8 @@
 namespace osht {
 
 void launch_fold(const Plan& p, const double* Y, double* H, int64_t B, hipStream_t st);
-void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, double* f, int64_t B, hipStream_t st);
+void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, double* f, int64_t B, hipStream_t st,
+                           int64_t real_maps = 0);
 
 namespace {
 
@@ -408,7 +409,7 @@ void level_slots(const Plan& p, int am, int& s0, int& s1) {
 
 }  // namespace
 
-void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t st) {
+void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t st, int64_t real_maps) {
   ensure_workspace(p, B);
   const Geo g = geo(p, B);
   (void)g;
@@ -419,15 +420,15 @@ void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t s
     launch_fold(p, p.w_Y.as<double>(), p.w_H.as<double>(), B, st);
   }
   ProfScope ps(p.prof, "ring_synthesis", st);
-  launch_ring_synthesis(p, p.w_H.as<double>(), 0, f, B, st);
+  launch_ring_synthesis(p, p.w_H.as<double>(), 0, f, B, st, real_maps);
 }
 
-void run_forward_levels(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {
+void run_forward_levels(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st, int64_t real_maps) {
   ensure_workspace(p, B);
   const Geo g = geo(p, B);
   {
     ProfScope ps(p.prof, "ring_analysis", st);
-    launch_ring_analysis(p, f, p.w_H.as<double>(), B, true, st);
+    launch_ring_analysis(p, f, p.w_H.as<double>(), B, true, st, real_maps);
   }
   const dim3 blk(256);
   for (int am = p.L - 1; am >= 0; --am) {
@@ -494,9 +495,9 @@ void run_forward_adjoint(Plan& p, const double* flmbar, double* fbar, int64_t B,
   launch_ring_synthesis(p, p.w_H.as<double>(), 1, fbar, B, st);
 }
 
-void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {
-  if (p.fb.b > 1) run_forward_blocked(p, f, flm, B, st);
-  else run_forward_levels(p, f, flm, B, st);
+void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st, int64_t real_maps) {
+  if (p.fb.b > 1) run_forward_blocked(p, f, flm, B, st, real_maps);
+  else run_forward_levels(p, f, flm, B, st, real_maps);
 }
 
 // ---------------------------------------------------------------- real maps
@@ -521,28 +522,6 @@ __device__ __forceinline__ void lm_of(int64_t i, int& l, int& m) {
 __device__ __forceinline__ double2 reflect(const double2* __restrict__ x, int64_t i, int l, int m) {
   const double2 v = x[(int64_t)l * l + l - m];
   return (m & 1) ? make_double2(-v.x, v.y) : make_double2(v.x, -v.y);
-}
-
-// z[j] = f[2j] + i f[2j+1] (f[2j+1] = 0 past the batch)
-__global__ void pack_real_kernel(const double* __restrict__ f, double2* __restrict__ z, int64_t n, int64_t B,
-                                 int64_t Bc) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Bc * n; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = e / n, i = e - j * n;
-    const double a = f[2 * j * n + i];
-    const double b = 2 * j + 1 < B ? f[(2 * j + 1) * n + i] : 0.0;
-    z[e] = make_double2(a, b);
-  }
-}
-
-// f[2j] = Re z[j], f[2j+1] = Im z[j]
-__global__ void unpack_real_kernel(const double2* __restrict__ z, double* __restrict__ f, int64_t n, int64_t B,
-                                   int64_t Bc) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Bc * n; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = e / n, i = e - j * n;
-    const double2 v = z[e];
-    f[2 * j * n + i] = v.x;
-    if (2 * j + 1 < B) f[(2 * j + 1) * n + i] = v.y;
-  }
 }
 
 // zlm[j] = S(flm[2j]) + i S(flm[2j+1]), S(x) = (x + R(x))/2: the inverse of
@@ -589,21 +568,19 @@ dim3 elementwise_grid(int64_t n) { return dim3((unsigned)std::min<int64_t>(std::
 void real_workspace(Plan& p, int64_t Bc) {
   OSHT_CHECK(p.spin == 0, OSHT_ENOTSUP, "real-map transforms are defined for spin 0 only");
   const size_t bytes = sizeof(double) * 2 * (size_t)p.L * p.L * (size_t)Bc;
-  if (bytes > p.w_R1.bytes || bytes > p.w_R2.bytes) OSHT_HIP(hipDeviceSynchronize());
+  if (bytes > p.w_R1.bytes) OSHT_HIP(hipDeviceSynchronize());
   p.w_R1.reserve(bytes);
-  p.w_R2.reserve(bytes);
 }
 
 }  // namespace
 
+// The ring DFTs read and write the real maps directly (two per complex map);
+// only the coefficient side is packed and unpacked here.
 void run_forward_real(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {
   const int64_t Bc = (B + 1) / 2, n = (int64_t)p.L * p.L;
   real_workspace(p, Bc);
-  double2* z = p.w_R1.as<double2>();
-  double2* zlm = p.w_R2.as<double2>();
-  hipLaunchKernelGGL(pack_real_kernel, elementwise_grid(Bc * n), dim3(256), 0, st, f, z, n, B, Bc);
-  OSHT_HIP(hipGetLastError());
-  run_forward(p, reinterpret_cast<const double*>(z), reinterpret_cast<double*>(zlm), Bc, st);
+  double2* zlm = p.w_R1.as<double2>();
+  run_forward(p, f, reinterpret_cast<double*>(zlm), Bc, st, B);
   hipLaunchKernelGGL(unpack_coef_kernel, elementwise_grid(Bc * n), dim3(256), 0, st, zlm,
                      reinterpret_cast<double2*>(flm), n, B, Bc);
   OSHT_HIP(hipGetLastError());
@@ -613,13 +590,10 @@ void run_inverse_real(Plan& p, const double* flm, double* f, int64_t B, hipStrea
   const int64_t Bc = (B + 1) / 2, n = (int64_t)p.L * p.L;
   real_workspace(p, Bc);
   double2* zlm = p.w_R1.as<double2>();
-  double2* z = p.w_R2.as<double2>();
   hipLaunchKernelGGL(pack_coef_kernel, elementwise_grid(Bc * n), dim3(256), 0, st,
                      reinterpret_cast<const double2*>(flm), zlm, n, B, Bc);
   OSHT_HIP(hipGetLastError());
-  run_inverse(p, reinterpret_cast<const double*>(zlm), reinterpret_cast<double*>(z), Bc, st);
-  hipLaunchKernelGGL(unpack_real_kernel, elementwise_grid(Bc * n), dim3(256), 0, st, z, f, n, B, Bc);
-  OSHT_HIP(hipGetLastError());
+  run_inverse(p, reinterpret_cast<const double*>(zlm), f, Bc, st, B);
 }
 
 }  // namespace osht
