@@ -27,6 +27,10 @@ COMMON = [
     "-Wall",
     "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary VGPRs: otherwise the k loops of the
+    # GEMMs copy every accumulator to AGPRs and back (and drain the MFMA
+    # pipeline) once per k tile
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     f"-I{os.path.join(os.path.dirname(HERE), 'include')}",
 ]
 

@@ -271,7 +271,10 @@ __device__ __forceinline__ void wait_vm(int n) {
 // PREFC: C is read (beta != 0) into registers before the k loop, so that its
 // latency overlaps the streaming instead of following it (the forward's
 // correction, whose k depth is at most one block of levels).
-template <class T, int TK = TKS, int NS = NST, class TB = double, bool PREFC = false>
+// W22: the four waves cover the 64x64 tile as 2x2 blocks of 32x32 (each
+// 2x2 MFMA tiles of 16x16) instead of four 16x64 strips, so a wave reads two
+// A and two B operands from LDS per four MFMAs instead of one A and four B.
+template <class T, int TK = TKS, int NS = NST, class TB = double, bool PREFC = false, bool W22 = false>
 __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTask& t, char* smem) {
   typedef StreamShape<T, TK, TB> S;
   constexpr bool F64 = sizeof(T) == 8;
@@ -279,6 +282,9 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
   const int m0 = t.mt * TM, n0 = t.nt * TN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kq = lane >> 4, li = lane & 15;
+  // first row / column (within the tile) of MFMA tile nb of this wave
+  auto rowb = [&](int nb) { return W22 ? (wave & 1) * 32 + (nb >> 1) * 16 : wave * 16; };
+  auto colb = [&](int nb) { return W22 ? (wave >> 1) * 32 + (nb & 1) * 16 : nb * 16; };
   dbl4 acc[4];
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) acc[nb] = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -288,8 +294,8 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
     for (int nb = 0; nb < 4; ++nb) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = m0 + wave * 16 + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
-        const int col = n0 + nb * 16 + (lane & 15);
+        const int r = m0 + rowb(nb) + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+        const int col = n0 + colb(nb) + (lane & 15);
         cpre[nb][v] = (d.beta != 0.0 && r >= d.m_lo && r < d.M && col < d.N)
                           ? d.C[(int64_t)r * d.sCr + (int64_t)col * d.sCc]
                           : 0.0;
@@ -312,7 +318,21 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
     const char* stage = smem + (kt % NS) * S::STAGE;
     const T* As = reinterpret_cast<const T*>(stage);
     const TB* Bs = reinterpret_cast<const TB*>(stage + S::A_BYTES);
-    if constexpr (F64) {
+    if constexpr (F64 && W22) {
+#pragma unroll
+      for (int s = 0; s < TK / 4; ++s) {
+        const int k = 4 * s + kq;
+        double a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          a[i] = As[k * 64 + ((rowb(2 * i) + li) ^ S::aswz(k))];
+          b[i] = Bs[k * 64 + ((colb(i) + li) ^ S::bswz(k))];
+        }
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+          acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[nb >> 1], b[nb & 1], acc[nb], 0, 0, 0);
+      }
+    } else if constexpr (F64) {
 #pragma unroll
       for (int s = 0; s < TK / 4; ++s) {
         const int k = 4 * s + kq;
@@ -330,11 +350,23 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
 #pragma unroll
       for (int s = 0; s < TK / 4; ++s) {
         const int k = 4 * s + kq;
-        const float a = As[k * 64 + ((wave * 16 + li) ^ S::aswz(k))];
+        if constexpr (W22) {
+          float a[2], b[2];
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-          const float b = (float)Bs[k * 64 + ((nb * 16 + li) ^ S::bswz(k))];
-          c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c[nb], 0, 0, 0);
+          for (int i = 0; i < 2; ++i) {
+            a[i] = As[k * 64 + ((rowb(2 * i) + li) ^ S::aswz(k))];
+            b[i] = (float)Bs[k * 64 + ((colb(i) + li) ^ S::bswz(k))];
+          }
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb)
+            c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[nb >> 1], b[nb & 1], c[nb], 0, 0, 0);
+        } else {
+          const float a = As[k * 64 + ((wave * 16 + li) ^ S::aswz(k))];
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) {
+            const float b = (float)Bs[k * 64 + ((nb * 16 + li) ^ S::bswz(k))];
+            c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c[nb], 0, 0, 0);
+          }
         }
         if (TK > 16 && s % 4 == 3 && s + 1 < TK / 4) {  // FP32 partial sums cover 16 k at most
 #pragma unroll
@@ -355,8 +387,8 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
   for (int nb = 0; nb < 4; ++nb) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = m0 + wave * 16 + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
-      const int col = n0 + nb * 16 + (lane & 15);
+      const int r = m0 + rowb(nb) + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+      const int col = n0 + colb(nb) + (lane & 15);
       if (r >= d.m_lo && r < d.M && col < d.N) {
         const int64_t ci = (int64_t)r * d.sCr + (int64_t)col * d.sCc;
         if constexpr (std::is_same<TB, float>::value) {  // FP32 inverse apply: C may be FP32
@@ -381,9 +413,20 @@ static_assert(2 * TK * (TM + Pad<float>::v) * 2 * sizeof(float) <= kSmemDoubles 
 // Stream shape per role (k depth, stages), measured on MI355X: the inverse
 // apply (one full-occupancy launch) runs 32-deep tiles in 2 stages, the
 // forward's per-block launches (few workgroups each) 16-deep tiles in 3.
-template <class Role> struct StreamCfg { static constexpr int TK = 16, NS = 3; };
-template <> struct StreamCfg<RoleApplyInverse> { static constexpr int TK = 32, NS = 2; };
-template <> struct StreamCfg<RoleApplyInverse32> { static constexpr int TK = 32, NS = 2; };
+// NS32: stages of the tiles with an FP32 A and FP64 B.  (Four 12 KB stages
+// at k depth 16 fit the LDS of three FP64 ones but measured no faster.)
+template <class Role> struct StreamCfg {
+  static constexpr int TK = 16, NS = 3, NS32 = 3;
+  static constexpr bool W22 = true;
+};
+template <> struct StreamCfg<RoleApplyInverse> {
+  static constexpr int TK = 32, NS = 2, NS32 = 2;
+  static constexpr bool W22 = true;
+};
+template <> struct StreamCfg<RoleApplyInverse32> {
+  static constexpr int TK = 32, NS = 2, NS32 = 2;
+  static constexpr bool W22 = true;
+};
 
 // Each task's descriptor selects the matrix precision (GemmDesc::fp32).
 template <bool ARF, bool BCF, class Role>
@@ -391,8 +434,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
                                                    const GemmTask* __restrict__ tasks) {
   typedef StreamCfg<Role> SC;
   constexpr bool kF32 = std::is_same<Role, RoleApplyInverse32>::value;
-  constexpr int kStream =
-      SC::NS * (kF32 ? StreamShape<float, SC::TK, float>::STAGE : StreamShape<double, SC::TK>::STAGE) / 8;
+  constexpr int kStream64 = SC::NS * StreamShape<double, SC::TK>::STAGE / 8;
+  constexpr int kStream32 = SC::NS32 * StreamShape<float, SC::TK, double>::STAGE / 8;
+  constexpr int kStream = kF32 ? SC::NS * StreamShape<float, SC::TK, float>::STAGE / 8
+                               : (kStream64 > kStream32 ? kStream64 : kStream32);
   __shared__ __align__(16) double smem[kF32 ? kStream
                                              : (ARF && BCF) ? (kStream > kSmemDoubles ? kStream : kSmemDoubles)
                                                             : kSmemDoubles];
@@ -415,11 +460,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
   const GemmDesc d = descs[t.desc];
   // column-major A streams through LDS
   if constexpr (kF32) {
-    gemm_tile_stream<float, SC::TK, SC::NS, float>(d, t, reinterpret_cast<char*>(smem));
+    gemm_tile_stream<float, SC::TK, SC::NS, float, false, SC::W22>(d, t, reinterpret_cast<char*>(smem));
   } else if constexpr (ARF && BCF) {
     constexpr bool kPrefC = std::is_same<Role, RoleCorrection>::value;
-    if (d.fp32) gemm_tile_stream<float, SC::TK, SC::NS, double, kPrefC>(d, t, reinterpret_cast<char*>(smem));
-    else gemm_tile_stream<double, SC::TK, SC::NS, double, kPrefC>(d, t, reinterpret_cast<char*>(smem));
+    if (d.fp32) gemm_tile_stream<float, SC::TK, SC::NS32, double, kPrefC, SC::W22>(d, t, reinterpret_cast<char*>(smem));
+    else gemm_tile_stream<double, SC::TK, SC::NS, double, kPrefC, SC::W22>(d, t, reinterpret_cast<char*>(smem));
   } else {
     if (d.fp32) gemm_tile<ARF, BCF, float>(d, t, smem);
     else gemm_tile<ARF, BCF, double>(d, t, smem);
