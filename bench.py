@@ -147,6 +147,7 @@ def apply_peak(path, f32, f64):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_forward_L1024_B16.md")
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_1403_4661_amd", "csrc", f) for f in ("gemm.hip", "transform.hip", "sweep.hip")]
+TRAFFIC_SOURCES.append(os.path.join(ROOT, "paper_1403_4661_amd", "build.py"))  # compiler flags
 
 
 def measured_traffic(path, L, B, launches_per_step):
