@@ -208,6 +208,8 @@ struct StreamShape {
   static constexpr int RPI = 64 / LPR;            // B rows per wave load (2 | 4)
   static constexpr int NIB = TK / RPI;            // wave loads per B tile
   static constexpr int PER_WAVE = (NIA + NIB) / 4;
+  // every wave issues PER_WAVE loads per stage (the vmcnt waits count on it)
+  static_assert(NIA % 4 == 0 && NIB % 4 == 0, "stream loads must split evenly over the four waves");
   static constexpr int A_BYTES = 64 * TK * ES;
   static constexpr int STAGE = A_BYTES + TK * 64 * EB;
   static __device__ __forceinline__ int aswz(int k) { return ES == 8 ? 16 * (k & 1) : 16 * (k & 3); }
@@ -411,12 +413,13 @@ constexpr int kSmemDoubles = 2 * 2 * TK * (TM + Pad<double>::v);
 static_assert(2 * TK * (TM + Pad<float>::v) * 2 * sizeof(float) <= kSmemDoubles * sizeof(double), "LDS size");
 
 // Stream shape per role (k depth, stages), measured on MI355X: the inverse
-// apply (one full-occupancy launch) runs 32-deep tiles in 2 stages, the
-// forward's per-block launches (few workgroups each) 16-deep tiles in 3.
-// NS32: stages of the tiles with an FP32 A and FP64 B.  (Four 12 KB stages
-// at k depth 16 fit the LDS of three FP64 ones but measured no faster.)
+// apply (one full-occupancy launch) runs 32-deep tiles in 2 stages; the
+// forward's per-block launches 16-deep tiles, FP64 ones in 2 stages (32 KB)
+// and those with an FP32 A and FP64 B (NS32) in 3 (36 KB), so that four
+// workgroups fit a CU's LDS (three FP64 stages, 48 KB, allowed three: the
+// step was 0.03-0.09 ms slower).
 template <class Role> struct StreamCfg {
-  static constexpr int TK = 16, NS = 3, NS32 = 3;
+  static constexpr int TK = 16, NS = 2, NS32 = 3;
   static constexpr bool W22 = true;
 };
 template <> struct StreamCfg<RoleApplyInverse> {
