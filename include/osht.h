@@ -97,6 +97,22 @@ typedef struct {
  * Returns OSHT_EINVAL for L < 1 or a NULL output array.
  */
 int osht_theta_greedy(int L, int32_t* numerators_out, double* kappa_out);
+/*
+ * The same greedy (Sec. III-D) computed on the current HIP device: per order,
+ * the candidate rows, S = B^T B (rocBLAS dgemm), its tridiagonal reduction and
+ * Q^T r for every candidate (rocSOLVER dsytrd / dormtr), and one secular
+ * solve per candidate in a kernel; the choice and its tie rule as above.
+ * rocBLAS and rocSOLVER are opened at the first call.  Synchronous; uses the
+ * null stream; allocates about 6 L^2 doubles of device memory for the call.
+ *   numerators_out / kappa_out: host arrays as for osht_theta_greedy.
+ * Returns OSHT_EINVAL for bad arguments, OSHT_ENOTSUP when rocBLAS or
+ * rocSOLVER cannot be opened, OSHT_ENOMEM / OSHT_EHIP on device failures.
+ * osht_plan_create uses it when the placement cache has no file for L (and
+ * the host greedy when the libraries cannot be opened).
+ * Currently switched off: returns OSHT_ENOTSUP (an unexplained GPU memory
+ * fault is under investigation); plans use the host greedy.
+ */
+int osht_theta_greedy_device(int L, int32_t* numerators_out, double* kappa_out);
 /* Eq. sampling_latitude: even k take 2L-1-k, odd k take k. */
 int osht_theta_alternating(int L, int32_t* numerators_out);
 

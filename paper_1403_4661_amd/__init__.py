@@ -28,11 +28,13 @@ __all__ = ["Plan", "InverseSHT", "ForwardSHT", "theta_greedy", "theta_alternatin
 THETA_CACHE_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "theta")
 
 
-def theta_greedy(L, with_kappa=False):
-    """Greedy colatitude numerators n_k (host computation in the library)."""
+def theta_greedy(L, with_kappa=False, device=False):
+    """Greedy colatitude numerators n_k, computed by the library on the host
+    or (device=True) on the current GPU."""
     num = (ctypes.c_int32 * L)()
     kap = (ctypes.c_double * L)()
-    _lib.check(lib().osht_theta_greedy(L, num, kap))
+    fn = lib().osht_theta_greedy_device if device else lib().osht_theta_greedy
+    _lib.check(fn(L, num, kap))
     out = [int(v) for v in num]
     return (out, [float(v) for v in kap]) if with_kappa else out
 

@@ -28,6 +28,7 @@ OSHT_TUNE = 0x100
 
 EXPORTED = (
     "osht_theta_greedy",
+    "osht_theta_greedy_device",
     "osht_theta_alternating",
     "osht_plan_create",
     "osht_plan_destroy",
@@ -102,6 +103,7 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     vp, i32p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
     L.osht_theta_greedy.argtypes = [ctypes.c_int, i32p, dp]
+    L.osht_theta_greedy_device.argtypes = [ctypes.c_int, i32p, dp]
     L.osht_theta_alternating.argtypes = [ctypes.c_int, i32p]
     L.osht_plan_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.c_char_p,
                                    ctypes.POINTER(vp)]

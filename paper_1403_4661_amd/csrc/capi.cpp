@@ -166,6 +166,18 @@ int osht_theta_greedy(int L, int32_t* numerators_out, double* kappa_out) {
   return OSHT_OK;
 }
 
+int osht_theta_greedy_device(int L, int32_t* numerators_out, double* kappa_out) {
+  if (L < 1 || L > 4096 || !numerators_out) return fail(OSHT_EINVAL, "L must be in [1, 4096] and the output non-NULL");
+  try {
+    osht::theta_greedy_device(L, numerators_out, kappa_out);
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(OSHT_ENOMEM, "host allocation failed");
+  }
+  return OSHT_OK;
+}
+
 int osht_theta_alternating(int L, int32_t* numerators_out) {
   if (L < 1 || L > 4096 || !numerators_out) return fail(OSHT_EINVAL, "L must be in [1, 4096] and the output non-NULL");
   osht::theta_alternating(L, numerators_out);
@@ -205,7 +217,8 @@ int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_di
       if (got == 0) {
         std::vector<double> kap(L);
         p.numer.assign(L, 0);
-        osht::theta_greedy(L, p.numer.data(), kap.data());
+        if (osht::theta_greedy_device_available(nullptr)) osht::theta_greedy_device(L, p.numer.data(), kap.data());
+        else osht::theta_greedy(L, p.numer.data(), kap.data());
         if (theta_cache_dir) write_cache(cache_path(theta_cache_dir, L), p.numer, kap);
       }
     }

@@ -281,6 +281,10 @@ void run_forward_adjoint_blocked(Plan& p, const double* flmbar, double* fbar, in
 // placement (theta.cpp)
 int theta_greedy(int L, int32_t* num_out, double* kappa_out);
 void theta_alternating(int L, int32_t* num_out);
+// the greedy on the current HIP device (throws Error; OSHT_ENOTSUP when
+// rocBLAS / rocSOLVER cannot be opened)
+void theta_greedy_device(int L, int32_t* num_out, double* kappa_out);
+bool theta_greedy_device_available(std::string* why);
 
 constexpr int kTile = 64;
 

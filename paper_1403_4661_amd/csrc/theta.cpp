@@ -25,112 +25,10 @@
 #include <vector>
 
 #include "host_util.hpp"
+#include "secular.hpp"
 
 namespace osht {
 
-namespace {
-
-// Solve (T - lam I) x = y for symmetric tridiagonal T (diag a[0..n-1],
-// off-diagonal b[0..n-2]) by Gaussian elimination with partial pivoting.
-// Returns y^T x and writes |x|^2 to *xx.
-double tri_solve_dot(int n, const double* a, const double* b, double lam, const double* y,
-                     double* work, double* xx) {
-  double* u0 = work;          // pivot-row diagonal entries
-  double* u1 = work + n;      // first super-diagonal
-  double* u2 = work + 2 * n;  // second super-diagonal (from row swaps)
-  double* rh = work + 3 * n;  // transformed right-hand side
-  double* x = work + 4 * n;
-  const double tiny = std::numeric_limits<double>::min() * 16;
-  // current pivot-candidate row: (p0, p1, p2) at columns i, i+1, i+2
-  double p0 = a[0] - lam, p1 = (n > 1) ? b[0] : 0.0, p2 = 0.0, prh = y[0];
-  for (int i = 0; i < n - 1; ++i) {
-    const double r0 = b[i];
-    const double r1 = a[i + 1] - lam;
-    const double r2 = (i + 1 < n - 1) ? b[i + 1] : 0.0;
-    const double rrh = y[i + 1];
-    if (std::fabs(p0) >= std::fabs(r0)) {
-      const double piv = (p0 == 0.0) ? tiny : p0;
-      const double f = r0 / piv;
-      u0[i] = piv; u1[i] = p1; u2[i] = p2; rh[i] = prh;
-      p0 = r1 - f * p1; p1 = r2 - f * p2; p2 = 0.0; prh = rrh - f * prh;
-    } else {
-      const double f = p0 / r0;
-      u0[i] = r0; u1[i] = r1; u2[i] = r2; rh[i] = rrh;
-      p0 = p1 - f * r1; p1 = p2 - f * r2; p2 = 0.0; prh = prh - f * rrh;
-    }
-  }
-  u0[n - 1] = (p0 == 0.0) ? tiny : p0;
-  rh[n - 1] = prh;
-  double dot = 0.0, nrm = 0.0;
-  for (int i = n - 1; i >= 0; --i) {
-    double v = rh[i];
-    if (i + 1 < n) v -= u1[i] * x[i + 1];
-    if (i + 2 < n) v -= u2[i] * x[i + 2];
-    x[i] = v / u0[i];
-    dot += y[i] * x[i];
-    nrm += x[i] * x[i];
-  }
-  *xx = nrm;
-  return dot;
-}
-
-// Number of eigenvalues of T below x (Sturm count from the LDL^T pivots).
-int sturm_count(int n, const double* a, const double* b, double x) {
-  int cnt = 0;
-  double q = a[0] - x;
-  const double tiny = std::numeric_limits<double>::min() * 16;
-  if (q < 0) ++cnt;
-  for (int i = 1; i < n; ++i) {
-    if (q == 0.0) q = tiny;
-    q = (a[i] - x) - b[i - 1] * b[i - 1] / q;
-    if (q < 0) ++cnt;
-  }
-  return cnt;
-}
-
-// k-th smallest eigenvalue of T (k = 0..n-1) by bisection on the Sturm count.
-double tri_eig(int n, const double* a, const double* b, int k) {
-  double lo = a[0], hi = a[0];
-  for (int i = 0; i < n; ++i) {
-    double r = 0.0;
-    if (i > 0) r += std::fabs(b[i - 1]);
-    if (i < n - 1) r += std::fabs(b[i]);
-    lo = std::min(lo, a[i] - r);
-    hi = std::max(hi, a[i] + r);
-  }
-  for (int it = 0; it < 200; ++it) {
-    double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    if (sturm_count(n, a, b, mid) > k) hi = mid; else lo = mid;
-  }
-  return 0.5 * (lo + hi);
-}
-
-// Root of phi(base + t) for t in (lo, hi), phi increasing there; geometric
-// bisection in t when `geometric` is set (lo > 0), Newton steps when they
-// stay in the bracket.  Returns base + t at the root.
-double secular_root(int n, const double* a, const double* b, const double* y, double base,
-                    double lo, double hi, bool geometric, double* work) {
-  auto mid = [&]() { return geometric ? std::sqrt(lo * hi) : 0.5 * (lo + hi); };
-  double t = mid();
-  for (int it = 0; it < 400; ++it) {
-    double xx;
-    const double phi = 1.0 + tri_solve_dot(n, a, b, base + t, y, work, &xx);
-    if (phi == 0.0) return base + t;
-    if (phi < 0.0) lo = t; else hi = t;
-    if (hi - lo <= 4e-16 * hi) return base + 0.5 * (lo + hi);
-    double nxt = t - phi / xx;  // phi' = |x|^2
-    if (!(nxt > lo && nxt < hi)) {
-      nxt = mid();
-    } else if (std::fabs(nxt - t) <= 4e-16 * std::fabs(t)) {
-      return base + nxt;  // Newton has converged to rounding level
-    }
-    t = nxt;
-  }
-  return base + t;
-}
-
-}  // namespace
 
 // Greedy placement.  num_out[k] = n_k; kappa_out[m] = cond_2(P_m) (may be
 // nullptr).  Returns 0.
@@ -228,12 +126,12 @@ int theta_greedy(int L, int32_t* num_out, double* kappa_out) {
       // mu1 is the (numerically tiny) zero eigenvalue of S; the smallest
       // eigenvalue of S + r r^T lies in (mu1, mu2), the largest in
       // (mun, mun + |r|^2).
-      const double mu1 = tri_eig(n, av.data(), bv.data(), 0);
-      const double mu2 = tri_eig(n, av.data(), bv.data(), 1);
-      const double mun = tri_eig(n, av.data(), bv.data(), n - 1);
+      const double mu1 = secular::tri_eig(n, av.data(), bv.data(), 0);
+      const double mu2 = secular::tri_eig(n, av.data(), bv.data(), 1);
+      const double mun = secular::tri_eig(n, av.data(), bv.data(), n - 1);
       parallel_for(0, nc, [&](int64_t c) {
         std::vector<double> y(rows.begin() + (size_t)cand[c] * n, rows.begin() + (size_t)(cand[c] + 1) * n);
-        std::vector<double> work(5 * n);
+        std::vector<double> work(4 * n);
         double rr = 0.0;
         for (double v : y) rr += v * v;
         if (rr == 0.0) return;  // zero row: singular, kappa stays inf
@@ -245,16 +143,8 @@ int theta_greedy(int L, int32_t* num_out, double* kappa_out) {
           dot *= betas[j];
           for (size_t i = 0; i < v.size(); ++i) y[j + 1 + i] -= dot * v[i];
         }
-        const double gap = mu2 - mu1;
-        // below ~1e-15 |S| the computed spectrum carries no information:
-        // kappa above ~1e7 reads as singular
-        const double t_lo = std::max(gap * std::ldexp(1.0, -200), 1e-15 * mun);
-        double xx;
-        if (1.0 + tri_solve_dot(n, av.data(), bv.data(), mu1 + t_lo, y.data(), work.data(), &xx) >= 0.0) return;
-        const double lmin = secular_root(n, av.data(), bv.data(), y.data(), mu1, t_lo, gap, true, work.data()) - mu1;
-        const double lmax = secular_root(n, av.data(), bv.data(), y.data(), mun, 0.0, rr * (1 + 1e-12) + 1e-300,
-                                         false, work.data());
-        kap[c] = std::sqrt(lmax / lmin);
+        kap[c] = secular::candidate_kappa(n, av.data(), bv.data(), secular::View<const double>{y.data(), 1}, rr, mu1,
+                                          mu2, mun, secular::View<double>{work.data(), 1});
       }, 1);
     }
     double kmin = INFINITY;

@@ -109,3 +109,11 @@ def test_single_hip_runtime_in_process():
             "print(len(set(l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l)))")
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, check=True)
     assert out.stdout.strip() == "1"
+
+
+def test_device_greedy_is_switched_off():
+    """osht_theta_greedy_device reports OSHT_ENOTSUP (switched off) after
+    checking its arguments, without touching a device."""
+    lib = _lib()
+    assert lib.osht_theta_greedy_device(0, (ctypes.c_int32 * 1)(), None) == -1
+    assert lib.osht_theta_greedy_device(8, (ctypes.c_int32 * 8)(), None) == -5
