@@ -285,16 +285,25 @@ __global__ __launch_bounds__(64 * kDeltaWaves) void delta_apply_kernel(
   const int c0 = col0 + (lane & 15), c1 = c0 + 16;
   const bool rok = r < nu, c0ok = c0 < J, c1ok = c1 < J;
   dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  // batches of four k-steps, double-buffered in registers: the loads of
-  // batch i + 1 are in flight while batch i runs on the matrix cores; k
-  // beyond the wave's range loads zeros
+  // batches of four k-steps, double-buffered in registers: the data loads of
+  // batch i + 1 are in flight while batch i runs on the matrix cores, and the
+  // source-row indices they need were loaded one batch earlier still, so no
+  // batch waits on two dependent loads; k beyond the wave's range loads zeros
   double a[2][4], b0[2][4], b1[2][4];
-  auto load = [&](double* pa, double* pb0, double* pb1, int kbase) {
+  int yiA[4], yiB[4];
+  auto load_idx = [&](int* py, int kbase) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = kbase + 4 * t + q;
+      py[t] = k < ke ? src_yrow[s0 + k] : 0;
+    }
+  };
+  auto load = [&](double* pa, double* pb0, double* pb1, const int* py, int kbase) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int k = kbase + 4 * t + q;
       const bool kok = k < ke;
-      const int yr = kok ? src_yrow[s0 + k] : 0;
+      const int yr = py[t];
       const double* yrow = Y + (int64_t)(yr >> 1) * g.ncols + ((yr & 1) ? J : 0);
       pa[t] = (rok && kok) ? Minv[(int64_t)k * ld + r] : 0.0;
       pb0[t] = (c0ok && kok) ? yrow[c0] : 0.0;
@@ -309,12 +318,17 @@ __global__ __launch_bounds__(64 * kDeltaWaves) void delta_apply_kernel(
     }
   };
   const int nbat = ke > kb ? (ke - kb + 15) / 16 : 0;
-  if (nbat > 0) load(a[0], b0[0], b1[0], kb);
+  // at the top of each pair: a[0] holds batch i, yiB the indices of batch i+1
+  if (nbat > 0) load_idx(yiA, kb);
+  if (nbat > 1) load_idx(yiB, kb + 16);
+  if (nbat > 0) load(a[0], b0[0], b1[0], yiA, kb);
   for (int i = 0; i < nbat; i += 2) {
-    if (i + 1 < nbat) load(a[1], b0[1], b1[1], kb + 16 * (i + 1));
+    if (i + 2 < nbat) load_idx(yiA, kb + 16 * (i + 2));
+    if (i + 1 < nbat) load(a[1], b0[1], b1[1], yiB, kb + 16 * (i + 1));
     mfma4(a[0], b0[0], b1[0]);
     if (i + 1 < nbat) {
-      if (i + 2 < nbat) load(a[0], b0[0], b1[0], kb + 16 * (i + 2));
+      if (i + 3 < nbat) load_idx(yiB, kb + 16 * (i + 3));
+      if (i + 2 < nbat) load(a[0], b0[0], b1[0], yiA, kb + 16 * (i + 2));
       mfma4(a[1], b0[1], b1[1]);
     }
   }
