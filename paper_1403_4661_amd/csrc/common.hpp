@@ -195,7 +195,6 @@ struct Plan {
   int max_logM = 0;
   // per-call workspace (grown on demand)
   DevBuf w_X, w_Y, w_H, w_T, w_D;
-  DevBuf w_R1;                // packed complex coefficients of the real-map transforms
   FwdBlocks fb;
   std::vector<int32_t> h_btask_ptr;   // per block: [fwd, corr, end) offsets into d_btask
   DevBuf d_btask;
@@ -235,8 +234,9 @@ struct ProfScope {
 // plan construction (plan.hip)
 void build_plan(Plan& p);
 // transforms (transform.hip)
-// real_maps > 0: the samples f are real_maps real maps (float64), two per
-// complex map of the batch B = ceil(real_maps / 2)
+// real_maps > 0: the samples f and the coefficients flm are real_maps real
+// maps (float64 samples, complex128 coefficients), two per complex map of
+// the batch B = ceil(real_maps / 2)
 void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t st, int64_t real_maps = 0);
 void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st, int64_t real_maps = 0);
 void run_inverse_adjoint(Plan& p, const double* fbar, double* flmbar, int64_t B, hipStream_t st);

@@ -338,7 +338,7 @@ int64_t Plan::device_bytes() const {
                           &fb.d_slot_list, &fb.d_lev_ptr, &fb.d_unk_slot, &fb.d_unk_r, &fb.d_unk_m, &fb.d_src_ptr,
                           &fb.d_src_slot, &fb.d_src_row, &fb.d_src_m, &fb.d_w_ptr, &fb.d_w_col, &fb.d_w_val,
                           &fb.d_wide_slot, &fb.d_wide_row, &fb.d_wt_ptr, &fb.d_wt_row, &fb.d_wt_val, &fb.d_minv,
-                          &fb.d_src_yrow, &d_atask, &w_R1})
+                          &fb.d_src_yrow, &d_atask})
     n += b->bytes;
   return (int64_t)n;
 }

@@ -781,7 +781,7 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
       gemm_tasks_launch(p, bt + tp[1], tp[2] - tp[1], GemmRole::Correction, "apply_forward_correction", st);
     }
   }
-  launch_fwd_scatter(p, p.w_Y.as<double>(), flm, B, st);
+  launch_fwd_scatter(p, p.w_Y.as<double>(), flm, B, st, real_maps);
 }
 
 bool fwd_blocks_fit(Plan& p, int b) {

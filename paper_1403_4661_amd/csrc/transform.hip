@@ -337,15 +337,121 @@ void ensure_workspace(Plan& p, int64_t B) {
 
 void prepare_transforms(Plan& p, int64_t B) { ensure_workspace(p, B); }
 
-void launch_fwd_scatter(const Plan& p, const double* Y, double* flm, int64_t B, hipStream_t st) {
+namespace {
+
+// Real maps (spin 0): complex map j carries real maps 2j and 2j+1 as
+// z = S(a) + i S(b), S(x)_lm = (x_lm + (-1)^m conj(x_{l,-m})) / 2 (Eq.
+// yellm:conj; the inverse of S(x) is the real part of the inverse of x).  In
+// the slot row (l, |m|) of map j, P = z_{l,|m|} sits in the +m columns and
+// N = (-1)^m z_{l,-|m|} in the -m columns, so with alpha = S(a)_{l,|m|} and
+// beta = S(b)_{l,|m|}:  P = alpha + i beta,  N = conj(alpha) + i conj(beta);
+// and back:  a_{l,|m|} = (P + conj N)/2,  a_{l,-|m|} = (-1)^m (N + conj P)/2,
+// b_{l,|m|} = (P - conj N)/(2i),  b_{l,-|m|} = (-1)^m (N - conj P)/(2i).
+// One workgroup per (degree l, 64 orders |m|), 8 complex maps per LDS step.
+// Order 0 has only the +m columns (its -m columns are not read).
+template <class O>
+__global__ __launch_bounds__(256) void real_coef_to_slots_kernel(Geo g, int Breal, const double2* __restrict__ flm,
+                                                                 O* __restrict__ X) {
+  __shared__ double2 ta[2][16][65];  // [sign][real map in chunk][order in chunk]
+  const int l = blockIdx.y, am0 = 64 * (int)blockIdx.x;
+  if (am0 > l) return;  // uniform over the workgroup
+  const int nam = min(64, l - am0 + 1);
+  const int nc = g.ncols >> 1;
+  const int64_t LL = (int64_t)g.L * g.L;
+  for (int j0 = 0; j0 < g.B; j0 += 8) {
+    const int nj = min(8, g.B - j0);
+    for (int e = threadIdx.x; e < 2 * 2 * nj * nam; e += blockDim.x) {
+      const int ai = e % nam, rest = e / nam;
+      const int rr = rest % (2 * nj), sg = rest / (2 * nj);
+      const int r = 2 * j0 + rr, m = sg ? -(am0 + ai) : am0 + ai;
+      ta[sg][rr][ai] = r < Breal ? flm[(int64_t)r * LL + (int64_t)l * l + l + m] : double2{0.0, 0.0};
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nam * 2 * nj; e += blockDim.x) {
+      const int col = e % (2 * nj), ai = e / (2 * nj);
+      const int sg = col / nj, jj = col - sg * nj;
+      const int am = am0 + ai;
+      if (am == 0 && sg) continue;
+      const double s = (am & 1) ? -1.0 : 1.0;
+      const double2 ap = ta[0][2 * jj][ai], an = ta[1][2 * jj][ai];
+      const double2 bp = ta[0][2 * jj + 1][ai], bn = ta[1][2 * jj + 1][ai];
+      const double2 al = {0.5 * (ap.x + s * an.x), 0.5 * (ap.y - s * an.y)};
+      const double2 be = {0.5 * (bp.x + s * bn.x), 0.5 * (bp.y - s * bn.y)};
+      O o;
+      if (!sg) { o.x = al.x - be.y; o.y = al.y + be.x; }
+      else { o.x = al.x + be.y; o.y = be.x - al.y; }
+      X[((int64_t)am * g.L + (l - am)) * nc + sg * g.B + j0 + jj] = o;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void real_slots_to_coef_kernel(Geo g, int Breal, const double2* __restrict__ Y,
+                                                                 double2* __restrict__ flm) {
+  __shared__ double2 ty[2][8][65];  // [sign][complex map in chunk][order in chunk]
+  const int l = blockIdx.y, am0 = 64 * (int)blockIdx.x;
+  if (am0 > l) return;
+  const int nam = min(64, l - am0 + 1);
+  const int nc = g.ncols >> 1;
+  const int64_t LL = (int64_t)g.L * g.L;
+  for (int j0 = 0; j0 < g.B; j0 += 8) {
+    const int nj = min(8, g.B - j0);
+    for (int e = threadIdx.x; e < nam * 2 * nj; e += blockDim.x) {
+      const int col = e % (2 * nj), ai = e / (2 * nj);
+      const int sg = col / nj, jj = col - sg * nj;
+      const int am = am0 + ai;
+      const int c = (am == 0) ? jj : sg * g.B + jj;  // order 0: N is P
+      ty[sg][jj][ai] = Y[((int64_t)am * g.L + (l - am)) * nc + j0 + c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * 2 * nj * nam; e += blockDim.x) {
+      const int ai = e % nam, rest = e / nam;
+      const int rr = rest % (2 * nj), sg = rest / (2 * nj);
+      const int r = 2 * j0 + rr, am = am0 + ai;
+      if (r >= Breal || (am == 0 && sg)) continue;
+      const int jj = rr >> 1;
+      const double2 P = ty[0][jj][ai], N = ty[1][jj][ai];
+      const double s = sg ? ((am & 1) ? -1.0 : 1.0) : 1.0;
+      // sg = 0: (P + conj N)/2 and (P - conj N)/(2i); sg = 1: the same with P, N swapped, times (-1)^m
+      const double2 u = sg ? N : P, w = sg ? P : N;
+      double2 v;
+      if (rr & 1) { v.x = 0.5 * s * (u.y + w.y); v.y = -0.5 * s * (u.x - w.x); }
+      else { v.x = 0.5 * s * (u.x + w.x); v.y = 0.5 * s * (u.y - w.y); }
+      flm[(int64_t)r * LL + (int64_t)l * l + l + (sg ? -am : am)] = v;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+void launch_fwd_scatter(const Plan& p, const double* Y, double* flm, int64_t B, hipStream_t st, int64_t real_maps) {
   const Geo g = geo(p, B);
+  if (real_maps > 0) {
+    hipLaunchKernelGGL(real_slots_to_coef_kernel, dim3((unsigned)ceil_div(p.L, 64), p.L), dim3(256), 0, st, g,
+                       (int)real_maps, reinterpret_cast<const double2*>(Y), reinterpret_cast<double2*>(flm));
+    OSHT_HIP(hipGetLastError());
+    return;
+  }
   hipLaunchKernelGGL(coef_transpose_kernel<false>, dim3((unsigned)ceil_div(2 * p.L - 1, 64), p.L), dim3(256), 0, st, g,
                      reinterpret_cast<const double2*>(Y), reinterpret_cast<double2*>(flm));
   OSHT_HIP(hipGetLastError());
 }
 
-void launch_coef_to_slots(const Plan& p, const double* flm, double* X, int64_t B, hipStream_t st, bool f32) {
+void launch_coef_to_slots(const Plan& p, const double* flm, double* X, int64_t B, hipStream_t st, bool f32,
+                          int64_t real_maps = 0) {
   const Geo g = geo(p, B);
+  if (real_maps > 0) {
+    const dim3 rgrid((unsigned)ceil_div(p.L, 64), p.L);
+    if (f32)
+      hipLaunchKernelGGL(real_coef_to_slots_kernel<float2>, rgrid, dim3(256), 0, st, g, (int)real_maps,
+                         reinterpret_cast<const double2*>(flm), reinterpret_cast<float2*>(X));
+    else
+      hipLaunchKernelGGL(real_coef_to_slots_kernel<double2>, rgrid, dim3(256), 0, st, g, (int)real_maps,
+                         reinterpret_cast<const double2*>(flm), reinterpret_cast<double2*>(X));
+    OSHT_HIP(hipGetLastError());
+    return;
+  }
   const dim3 grid((unsigned)ceil_div(2 * p.L - 1, 64), p.L);
   if (f32)
     hipLaunchKernelGGL((coef_transpose_kernel<true, float2>), grid, dim3(256), 0, st, g,
@@ -413,7 +519,7 @@ void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t s
   ensure_workspace(p, B);
   const Geo g = geo(p, B);
   (void)g;
-  launch_coef_to_slots(p, flm, p.w_X.as<double>(), B, st, p.fp32);
+  launch_coef_to_slots(p, flm, p.w_X.as<double>(), B, st, p.fp32, real_maps);
   gemm_slots(p, kInv, 0, p.nslots, st);
   {
     ProfScope ps(p.prof, "fold", st);
@@ -452,7 +558,7 @@ void run_forward_levels(Plan& p, const double* f, double* flm, int64_t B, hipStr
       }
     }
   }
-  launch_fwd_scatter(p, p.w_Y.as<double>(), flm, B, st);
+  launch_fwd_scatter(p, p.w_Y.as<double>(), flm, B, st, real_maps);
 }
 
 void run_inverse_adjoint(Plan& p, const double* fbar, double* flmbar, int64_t B, hipStream_t st) {
@@ -464,7 +570,7 @@ void run_inverse_adjoint(Plan& p, const double* fbar, double* flmbar, int64_t B,
                      p.w_X.as<double>());
   OSHT_HIP(hipGetLastError());
   gemm_slots(p, kIadj, 0, p.nslots, st);
-  launch_fwd_scatter(p, p.w_Y.as<double>(), flmbar, B, st);
+  launch_fwd_scatter(p, p.w_Y.as<double>(), flmbar, B, st, 0);
 }
 
 void run_forward_adjoint(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st) {
@@ -511,89 +617,23 @@ void run_forward(Plan& p, const double* f, double* flm, int64_t B, hipStream_t s
 
 namespace {
 
-__device__ __forceinline__ void lm_of(int64_t i, int& l, int& m) {
-  l = (int)sqrt((double)i);
-  while ((int64_t)l * l > i) --l;
-  while ((int64_t)(l + 1) * (l + 1) <= i) ++l;
-  m = (int)(i - (int64_t)l * l - l);
-}
-
-// R(x)_lm = (-1)^m conj(x_{l,-m}) of one map's coefficients
-__device__ __forceinline__ double2 reflect(const double2* __restrict__ x, int64_t i, int l, int m) {
-  const double2 v = x[(int64_t)l * l + l - m];
-  return (m & 1) ? make_double2(-v.x, v.y) : make_double2(v.x, -v.y);
-}
-
-// zlm[j] = S(flm[2j]) + i S(flm[2j+1]), S(x) = (x + R(x))/2: the inverse of
-// S(x) is the real part of the inverse of x, so any input is accepted
-__global__ void pack_coef_kernel(const double2* __restrict__ flm, double2* __restrict__ z, int64_t n, int64_t B,
-                                 int64_t Bc) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Bc * n; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = e / n, i = e - j * n;
-    int l, m;
-    lm_of(i, l, m);
-    const double2* a = flm + 2 * j * n;
-    const double2 av = a[i], ar = reflect(a, i, l, m);
-    double2 s = make_double2(0.5 * (av.x + ar.x), 0.5 * (av.y + ar.y));
-    if (2 * j + 1 < B) {
-      const double2* b = flm + (2 * j + 1) * n;
-      const double2 bv = b[i], br = reflect(b, i, l, m);
-      const double2 t = make_double2(0.5 * (bv.x + br.x), 0.5 * (bv.y + br.y));
-      s.x -= t.y;  // + i t
-      s.y += t.x;
-    }
-    z[e] = s;
-  }
-}
-
-// flm[2j] = (z + R(z))/2, flm[2j+1] = (z - R(z))/(2i)
-__global__ void unpack_coef_kernel(const double2* __restrict__ z, double2* __restrict__ flm, int64_t n, int64_t B,
-                                   int64_t Bc) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Bc * n; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = e / n, i = e - j * n;
-    int l, m;
-    lm_of(i, l, m);
-    const double2* zj = z + j * n;
-    const double2 v = zj[i], r = reflect(zj, i, l, m);
-    flm[2 * j * n + i] = make_double2(0.5 * (v.x + r.x), 0.5 * (v.y + r.y));
-    if (2 * j + 1 < B) {
-      const double dx = 0.5 * (v.x - r.x), dy = 0.5 * (v.y - r.y);
-      flm[(2 * j + 1) * n + i] = make_double2(dy, -dx);  // (dx + i dy) / i
-    }
-  }
-}
-
-dim3 elementwise_grid(int64_t n) { return dim3((unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(n, 256), 1), 8192)); }
-
-void real_workspace(Plan& p, int64_t Bc) {
+void check_real(const Plan& p) {
   OSHT_CHECK(p.spin == 0, OSHT_ENOTSUP, "real-map transforms are defined for spin 0 only");
-  const size_t bytes = sizeof(double) * 2 * (size_t)p.L * p.L * (size_t)Bc;
-  if (bytes > p.w_R1.bytes) OSHT_HIP(hipDeviceSynchronize());
-  p.w_R1.reserve(bytes);
 }
 
 }  // namespace
 
-// The ring DFTs read and write the real maps directly (two per complex map);
-// only the coefficient side is packed and unpacked here.
+// Two real maps per complex transform: the ring DFTs read and write the real
+// samples directly, and the coefficient transposes pack and unpack the
+// conjugation-symmetric parts (no extra passes).
 void run_forward_real(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st) {
-  const int64_t Bc = (B + 1) / 2, n = (int64_t)p.L * p.L;
-  real_workspace(p, Bc);
-  double2* zlm = p.w_R1.as<double2>();
-  run_forward(p, f, reinterpret_cast<double*>(zlm), Bc, st, B);
-  hipLaunchKernelGGL(unpack_coef_kernel, elementwise_grid(Bc * n), dim3(256), 0, st, zlm,
-                     reinterpret_cast<double2*>(flm), n, B, Bc);
-  OSHT_HIP(hipGetLastError());
+  check_real(p);
+  run_forward(p, f, flm, (B + 1) / 2, st, B);
 }
 
 void run_inverse_real(Plan& p, const double* flm, double* f, int64_t B, hipStream_t st) {
-  const int64_t Bc = (B + 1) / 2, n = (int64_t)p.L * p.L;
-  real_workspace(p, Bc);
-  double2* zlm = p.w_R1.as<double2>();
-  hipLaunchKernelGGL(pack_coef_kernel, elementwise_grid(Bc * n), dim3(256), 0, st,
-                     reinterpret_cast<const double2*>(flm), zlm, n, B, Bc);
-  OSHT_HIP(hipGetLastError());
-  run_inverse(p, reinterpret_cast<const double*>(zlm), f, Bc, st, B);
+  check_real(p);
+  run_inverse(p, flm, f, (B + 1) / 2, st, B);
 }
 
 }  // namespace osht

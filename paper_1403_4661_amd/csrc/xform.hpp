@@ -55,7 +55,8 @@ __device__ __forceinline__ int64_t alias_index(const Geo& g, const Slot* __restr
 enum { kInv = 0, kFwd = 1, kIadj = 2, kFadj = 3, kCorr = 4, kFwdAlias = 5, kCorrAlias = 6, kFadjCorr = 7, kNumDir = 8 };
 
 void ensure_workspace(Plan& p, int64_t B);
-void launch_fwd_scatter(const Plan& p, const double* Y, double* flm, int64_t B, hipStream_t st);
+// real_maps > 0: flm holds real_maps real maps (two per complex map of the batch B)
+void launch_fwd_scatter(const Plan& p, const double* Y, double* flm, int64_t B, hipStream_t st, int64_t real_maps = 0);
 void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, GemmRole role, const char* prof_name,
                        hipStream_t st);
 
