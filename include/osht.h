@@ -141,7 +141,10 @@ int osht_plan_theta(const osht_plan_t* plan, int32_t* numerators_host);
  * Inverse SHT (Eq. f_inverse_SHT, Procedure 2): samples from coefficients.
  *   flm: device, batch * L*L complex128 (read)
  *   f:   device, batch * L*L complex128 (written); must not overlap flm.
- * batch >= 1.  Asynchronous on stream.
+ * batch >= 1.  Asynchronous on stream, except that a call with a larger
+ * batch than any earlier call on the plan first synchronizes the device while
+ * it grows the plan's workspace and rewrites its descriptor tables (the same
+ * holds for every transform entry point).
  */
 int osht_inverse(const osht_plan_t* plan, const void* flm, void* f, int64_t batch,
                  hipStream_t stream);
@@ -169,9 +172,9 @@ int osht_forward(const osht_plan_t* plan, const void* f, void* flm, int64_t batc
  *     f device, batch * L*L float64 (written): the real part of
  *     osht_inverse(flm), which is the whole of it when flm has the symmetry
  *     above.
- * In and out must not overlap.  Asynchronous on stream, except that a call
- * whose batch needs larger packing buffers synchronizes the device to grow
- * them.  Not accepted by osht_batch_run.
+ * In and out must not overlap.  Asynchronous on stream, with the workspace
+ * rule of osht_inverse for a batch of ceil(batch/2) complex maps.  Not
+ * accepted by osht_batch_run.
  */
 int osht_forward_real(const osht_plan_t* plan, const void* f, void* flm, int64_t batch,
                       hipStream_t stream);
