@@ -412,18 +412,19 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
 constexpr int kSmemDoubles = 2 * 2 * TK * (TM + Pad<double>::v);
 static_assert(2 * TK * (TM + Pad<float>::v) * 2 * sizeof(float) <= kSmemDoubles * sizeof(double), "LDS size");
 
-// Stream shape per role (k depth, stages), measured on MI355X: the inverse
-// apply (one full-occupancy launch) runs 32-deep tiles in 2 stages; the
-// forward's per-block launches 16-deep tiles, FP64 ones in 2 stages (32 KB)
-// and those with an FP32 A and FP64 B (NS32) in 3 (36 KB), so that four
-// workgroups fit a CU's LDS (three FP64 stages, 48 KB, allowed three: the
-// step was 0.03-0.09 ms slower).
+// Stream shape per role (k depth, stages), measured on MI355X.  FP64 tiles
+// run 16 deep in 2 stages (32 KB of LDS): in the forward's per-block
+// launches so that four workgroups fit a CU (three 48 KB stages allowed three
+// and the step was 0.03-0.09 ms slower), in the FP64 inverse apply 1.41 ->
+// 1.24 ms against 32-deep tiles (64 KB, two per CU).  Tiles with an FP32 A
+// and FP64 B (NS32) run in 3 stages (36 KB).  The FP32 inverse apply keeps
+// 32-deep tiles in 2 stages (32 KB); 3 stages of 32 or of 16 were no faster.
 template <class Role> struct StreamCfg {
   static constexpr int TK = 16, NS = 2, NS32 = 3;
   static constexpr bool W22 = true;
 };
 template <> struct StreamCfg<RoleApplyInverse> {
-  static constexpr int TK = 32, NS = 2, NS32 = 2;
+  static constexpr int TK = 16, NS = 2, NS32 = 2;
   static constexpr bool W22 = true;
 };
 template <> struct StreamCfg<RoleApplyInverse32> {
