@@ -417,11 +417,12 @@ static_assert(2 * TK * (TM + Pad<float>::v) * 2 * sizeof(float) <= kSmemDoubles 
 // launches so that four workgroups fit a CU (three 48 KB stages allowed three
 // and the step was 0.03-0.09 ms slower), in the FP64 inverse apply 1.41 ->
 // 1.24 ms against 32-deep tiles (64 KB, two per CU).  Tiles with an FP32 A
-// and FP64 B (NS32) run in 3 stages (36 KB).  The FP32 inverse apply runs
+// and FP64 B (NS32) run in 2 stages too (24 KB; 3 stages, 36 KB, were
+// slightly slower), so the forward blocks take 32 KB.  The FP32 inverse apply runs
 // 16-deep tiles in 2 stages (16 KB): 0.76 -> 0.74 ms against 32-deep ones;
 // 3 stages of 32 or of 16 were slower.
 template <class Role> struct StreamCfg {
-  static constexpr int TK = 16, NS = 2, NS32 = 3;
+  static constexpr int TK = 16, NS = 2, NS32 = 2;
   static constexpr bool W22 = true;
 };
 template <> struct StreamCfg<RoleApplyInverse> {
