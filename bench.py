@@ -428,7 +428,7 @@ def main():
             "frac": hp["apply_forward"]["tflops"] / peak,
             "traffic": measured_traffic(head, L, B, hp["apply_forward"]["launches"] // args.steps)}
     out = {
-        "metric": "fwd+inv SHT/s at L=1024, batch 16 (mixed vs FP64, max rel err); HBM GB/s",
+        "metric": f"fwd+inv SHT/s at L={L}, batch {B} (mixed vs FP64, max rel err); HBM GB/s",
         "value": hp["sht_per_s"],
         "unit": "SHT/s",
         "n_gpus": 1,
