@@ -270,14 +270,12 @@ __global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void chirp_kernel(const Rin
 // points.
 template <int LOGM>
 __device__ __forceinline__ void bluestein(cplx* v, const FftCtx& cx, const cplx* __restrict__ cf, bool active) {
-  // the chirp spectrum is loaded before the forward FFT, so that its latency
-  // overlaps the FFT (occupancy is set by LDS, so the registers are free)
-  cplx c[RPT];
-#pragma unroll
-  for (int i = 0; i < RPT; ++i) c[i] = active ? cf[cx.t + i * cx.T] : cplx{0.0, 0.0};
   fft<false, LOGM>(v, cx);
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) v[i] = cmul(v[i], c[i]);
+  for (int i = 0; i < RPT; ++i) {
+    const cplx c = active ? cf[cx.t + i * cx.T] : cplx{0.0, 0.0};
+    v[i] = cmul(v[i], c);
+  }
   fft<true, LOGM>(v, cx);
 }
 
