@@ -44,6 +44,7 @@ extern "C" {
 #define OSHT_ESINGULAR    -4  /* a per-order system P_m failed its inversion check */
 #define OSHT_ENOTSUP      -5  /* combination of flags not supported */
 #define OSHT_EIO          -6  /* placement cache file unreadable or malformed */
+#define OSHT_ENONFINITE   -7  /* a transform output held NaN or Inf (OSHT_CHECK_FINITE plans) */
 
 /* ------------------------------------------------------------------ flags */
 /* arithmetic of the order-wise apply (Procedure 1 step solve and alias
@@ -70,6 +71,15 @@ extern "C" {
  * the choice is cached in theta_cache_dir as "tune_fwd_<arch>_L<L>_s<s>_p<prec>.txt"
  * when that directory is given */
 #define OSHT_TUNE               0x100u
+/* run the forward (and forward adjoint) of a spin != 0 plan even when the
+ * plan-time self-check found it unstable (see osht_info_t.fwd_check_err);
+ * without this flag such calls return OSHT_ENOTSUP */
+#define OSHT_SPIN_FWD_FORCE     0x200u
+/* every transform of the plan scans its output for NaN / Inf on the device
+ * and records a hit in a sticky per-plan status read by osht_plan_status
+ * (one extra read of the output, 16 bytes per entry per map; off by
+ * default) */
+#define OSHT_CHECK_FINITE       0x400u
 
 typedef struct osht_plan osht_plan_t;
 
@@ -77,12 +87,21 @@ typedef struct {
   int32_t  L;
   int32_t  spin;
   uint32_t flags;
-  int32_t  reserved;
+  int32_t  fwd_unstable;    /* 1: spin != 0 plan whose forward failed the self-check below
+                               (forward calls return OSHT_ENOTSUP unless OSHT_SPIN_FWD_FORCE) */
   int64_t  nsamples;        /* L*L per map */
   int64_t  ncoeffs;         /* L*L per map */
   int64_t  device_bytes;    /* device memory held by the plan */
-  double   max_kappa;       /* max over m of cond_2 estimate of P_m */
-  double   max_inv_residual;/* max over m of |I - X_m P_m|_max after inversion */
+  double   max_kappa;       /* max over m of the 1-norm condition estimate of P_m */
+  double   max_inv_residual;/* max over m of |I - X_m P_m|_max of the stored inverses */
+  double   fwd_check_err;   /* plan-time self-check of the forward, in FP64: max |forward(inverse(a)) - a|
+                               / max |a| for one fixed pseudo-random band-limited a (entries uniform in
+                               [-1, 1] + i[-1, 1], zero for l < |s|).  The forward is exact on band-limited
+                               samples, so this measures how the order-by-order chain of Procedure 1
+                               amplifies rounding on this plan: ~1e-14 for spin 0 at L <= 512; for spin
+                               +-2 it grows from ~1e-11 at L = 8 to O(1) at L = 16 (the spin forward is
+                               unstable on this placement).  A spin != 0 plan with a value above 1e-8, or
+                               with max_inv_residual above 1e-10, is marked fwd_unstable. */
 } osht_info_t;
 
 /*
@@ -125,8 +144,14 @@ int osht_theta_alternating(int L, int32_t* numerators_out);
  * On the current HIP device: evaluates the Legendre (or Wigner) blocks
  * A_m[k, i] = sY_{l0+i}^m(theta_k, 0) in FP64 with adaptive rescaling
  * (Sec. III-F, III-G), inverts every P_m (rows k >= |m| of A_m; the least
- * squares pseudo-inverse when |m| < |s|) in FP64 on the GPU, and checks
- * |I - X_m P_m|_max < 1e-6 for each m (else OSHT_ESINGULAR).
+ * squares pseudo-inverse when |m| < |s|) in FP64 on the GPU by Newton-Schulz
+ * iteration, keeping each order's iterate with the smallest residual.
+ * Spin 0: every m must reach |I - X_m P_m|_max <= 1e-10, else the plan is
+ * refused with OSHT_ESINGULAR (the placement makes some P_m numerically
+ * singular, e.g. the alternating placement from L = 128 up).  Spin != 0: the
+ * inverses serve only the forward, so a larger residual marks the plan
+ * fwd_unstable instead.  Then runs the forward self-check described at
+ * osht_info_t.fwd_check_err (one inverse and one forward of a single map).
  * Synchronous: returns once the plan is ready.  *out receives the plan.
  */
 int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_dir,
@@ -155,6 +180,10 @@ int osht_inverse(const osht_plan_t* plan, const void* flm, void* f, int64_t batc
  * P_m f_m = g_m are solved (Eq. gtof_inverse, Eq. signal_update).
  *   f:   device, batch * L*L complex128 (read)
  *   flm: device, batch * L*L complex128 (written); must not overlap f.
+ * Returns OSHT_ENOTSUP, with nothing enqueued, on a plan marked fwd_unstable
+ * (spin != 0 above L ~ 9 on the greedy placement) unless the plan was
+ * created with OSHT_SPIN_FWD_FORCE; the same holds for osht_forward_adjoint
+ * and for forward jobs of osht_batch_run.
  */
 int osht_forward(const osht_plan_t* plan, const void* f, void* flm, int64_t batch,
                  hipStream_t stream);
@@ -249,6 +278,16 @@ int osht_graph_destroy(osht_graph_t* graph);
 int osht_plan_set_profiling(osht_plan_t* plan, int enable, const char* only_name);
 int osht_plan_kernel_time(osht_plan_t* plan, const char* name, int64_t* launches,
                           double* total_ms);
+
+/*
+ * Sticky output status of an OSHT_CHECK_FINITE plan: waits for the device
+ * to finish the work enqueued so far (hipDeviceSynchronize), stores OSHT_OK
+ * or OSHT_ENONFINITE in *status (the latter when any transform output since
+ * the last call held a NaN or an Inf) and clears the record.  On plans
+ * without the flag *status is always OSHT_OK.  Must not be called while a
+ * stream capture is in progress.
+ */
+int osht_plan_status(osht_plan_t* plan, int32_t* status);
 
 /* Human-readable message for a return code (static storage). */
 const char* osht_strerror(int code);

@@ -19,14 +19,18 @@ What each function follows:
 * inverse: Eq. f_inverse_SHT / Procedure 2 -- per order, G'_m on every ring
   from Eq. gm_integral, then f = sum_m G'_m(theta) e^{i m phi}, taken on each
   ring by folding order m into DFT bin (m mod n_k) and one inverse DFT.
-* forward: Procedure 1 as written, in the spatial domain: for |m| = L-1
-  down to 0, take ring |m|'s own (2|m|+1)-point DFT (all orders above |m|
-  have been removed from it by then; the reading of "(2m+1)-point FFT along
-  each ring" -- larger rings keep the DFT taken when they became clean),
-  gather g'_{+-m} from rings k >= |m|, solve P'_{+-m} f_{+-m} = g'_{+-m} by LU
-  (least squares via the pseudo-inverse when |m| < |s|, since then P'_m has
-  L-|m| rows and L-|s| unknowns), evaluate f~_m on rings k < |m| (Eq.
-  signal_subset) and subtract it from the samples (Eq. signal_update).
+* forward: block back-substitution in the sample domain.  The sampled
+  harmonic matrix is block triangular in descending |m|: ring k only sees
+  orders |m| <= k exactly, and orders above k alias into it.  So the orders
+  are recovered from the highest down.  When order |m| is reached, ring |m|
+  carries no higher order any more, its (2|m|+1)-point DFT is exact, and the
+  rings above it were made clean earlier (reading of "(2m+1)-point FFT along
+  each ring": every ring's own DFT, taken once it is clean).  Their bins
+  m mod n_k give g'_{+-m} (Eq. gm_integral), the order-m system of Eq.
+  gtof_inverse gives f_{+-m} (LU; least squares through the pseudo-inverse
+  when |m| < |s|, where P'_m has L-|m| rows and L-|s| unknowns), and the
+  order's field on the lower rings k < |m| (Eq. signal_subset) is
+  subtracted from their samples (Eq. signal_update).
 * inverse_adjoint / forward_adjoint: conjugate transposes with respect to the
   plain Euclidean inner products on C^{L^2} (the paper has no adjoints; the
   forward adjoint is the transpose of the Fourier-domain form of Procedure 1,
@@ -215,29 +219,42 @@ def inverse_rings(plan: Plan, flm, rings) -> dict:
     return out
 
 
+def _clean_ring_spectrum(work, k):
+    """(1/n_k) DFT of ring k's samples (exact once no order above k remains)."""
+    n = 2 * k + 1
+    return np.fft.fft(work[:, k * k:k * k + n], axis=1) / n
+
+
+def _order_field_on_lower_rings(plan: Plan, m: int, fm, geometry):
+    """Samples of order m's part of the signal, sum_l f_lm Y_lm, on rings
+    k < |m| (Eq. signal_subset), in ring-major order."""
+    ring, jj, nn = geometry
+    am = abs(m)
+    ns = am * am
+    g = fm @ plan.table(m)[:am, :].T  # G'_m(theta_k), k < |m|
+    phase = np.exp(2j * math.pi * ((m * jj[:ns]) % nn[:ns]) / nn[:ns])
+    return g[:, ring[:ns]] * phase[None, :]
+
+
 def forward(plan: Plan, f) -> np.ndarray:
-    """Coefficients from samples: Procedure 1, literally, in the spatial domain."""
+    """Coefficients from samples by sample-domain block back-substitution in
+    descending |m| (Eqs. gm_integral, gtof_inverse, signal_subset and
+    signal_update; see the module docstring)."""
     L = plan.L
     work = _as_batch(f, L).copy()
     B = work.shape[0]
     flm = np.zeros((B, L * L), dtype=np.complex128)
-    ring, jj, nn = ring_geometry(L)
-    spectra = [None] * L
+    geometry = ring_geometry(L)
+    spectra = {}
     for am in range(L - 1, -1, -1):
-        n = 2 * am + 1
-        spectra[am] = np.fft.fft(work[:, am * am:am * am + n], axis=1) / n
-        for m in ((am, -am) if am else (0,)):
-            l0 = plan.l0(m)
-            ks = np.arange(am, L)
-            g = np.stack([spectra[k][:, m % (2 * k + 1)] for k in ks], axis=1)
+        spectra[am] = _clean_ring_spectrum(work, am)
+        for m in sorted({am, -am}, reverse=True):
+            g = np.stack([spectra[k][:, m % (2 * k + 1)] for k in range(am, L)], axis=1)
             fm = plan.solve(m, g)
-            ell = np.arange(l0, L)
+            ell = np.arange(plan.l0(m), L)
             flm[:, ell * ell + ell + m] = fm
             if am > 0:
-                top = fm @ plan.table(m)[:am, :].T  # G'_m on rings k < |m|
-                ns = am * am
-                phase = np.exp(2j * math.pi * ((m * jj[:ns]) % nn[:ns]) / nn[:ns])
-                work[:, :ns] -= top[:, ring[:ns]] * phase[None, :]
+                work[:, :am * am] -= _order_field_on_lower_rings(plan, m, fm, geometry)
     return flm
 
 

@@ -49,13 +49,18 @@ class Plan:
     """A transform plan for band-limit L and spin s on the current device."""
 
     def __init__(self, L, spin=0, placement="greedy", precision="fp64", theta_cache_dir=THETA_CACHE_DIR,
-                 device=None, tune=False):
+                 device=None, tune=False, force_spin_forward=False, check_finite=False):
         """precision: "fp64" (FP64 throughout), "fp32" (inverse and its
         adjoint on FP32 A_m with FP32 matrix cores; the forward sweep, DFTs
         and buffers FP64) or "fp32-fwd" (also the forward's P_m^{-1} rows in
         FP32; its alias rows stay FP64).
         tune: time the forward sweep's block shapes on this device and keep
-        the fastest (cached in theta_cache_dir)."""
+        the fastest (cached in theta_cache_dir).
+        force_spin_forward: run the forward of a spin != 0 plan even when the
+        plan-time self-check marks it unstable (info()["fwd_unstable"]);
+        otherwise forward() and forward_adjoint() raise OshtError (ENOTSUP).
+        check_finite: every transform scans its output for NaN / Inf; read
+        the sticky result with status()."""
         import torch
 
         if placement not in ("greedy", "alternating"):
@@ -65,7 +70,9 @@ class Plan:
             raise ValueError("precision must be 'fp64', 'fp32' or 'fp32-fwd'")
         flags = prec[precision] | (
             _lib.OSHT_THETA_GREEDY if placement == "greedy" else _lib.OSHT_THETA_ALTERNATING) | (
-            _lib.OSHT_TUNE if tune else 0)
+            _lib.OSHT_TUNE if tune else 0) | (
+            _lib.OSHT_SPIN_FWD_FORCE if force_spin_forward else 0) | (
+            _lib.OSHT_CHECK_FINITE if check_finite else 0)
         self.L, self.spin, self.precision = int(L), int(spin), precision
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._h = ctypes.c_void_p()
@@ -77,7 +84,15 @@ class Plan:
     def info(self):
         info = _lib.OshtInfo()
         _lib.check(lib().osht_plan_info(self._h, ctypes.byref(info)))
-        return {f: getattr(info, f) for f, _ in info._fields_ if f != "reserved"}
+        return {f: getattr(info, f) for f, _ in info._fields_}
+
+    def status(self):
+        """Sticky output status (check_finite plans): OSHT_OK, or
+        OSHT_ENONFINITE when an output since the last call held NaN / Inf.
+        Waits for the device; clears the record."""
+        st = ctypes.c_int32()
+        _lib.check(lib().osht_plan_status(self._h, ctypes.byref(st)))
+        return int(st.value)
 
     def theta_numerators(self):
         num = (ctypes.c_int32 * self.L)()

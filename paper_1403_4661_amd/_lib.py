@@ -18,6 +18,7 @@ OSHT_EHIP = -3
 OSHT_ESINGULAR = -4
 OSHT_ENOTSUP = -5
 OSHT_EIO = -6
+OSHT_ENONFINITE = -7
 
 OSHT_PREC_FP64 = 0x0
 OSHT_PREC_FP32 = 0x1
@@ -25,6 +26,8 @@ OSHT_PREC_FP32_FWD = 0x2
 OSHT_THETA_GREEDY = 0x00
 OSHT_THETA_ALTERNATING = 0x10
 OSHT_TUNE = 0x100
+OSHT_SPIN_FWD_FORCE = 0x200
+OSHT_CHECK_FINITE = 0x400
 
 EXPORTED = (
     "osht_theta_greedy",
@@ -46,6 +49,7 @@ EXPORTED = (
     "osht_plan_kernel_time",
     "osht_batch_run",
     "osht_graph_destroy",
+    "osht_plan_status",
 )
 
 
@@ -54,12 +58,13 @@ class OshtInfo(ctypes.Structure):
         ("L", ctypes.c_int32),
         ("spin", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
-        ("reserved", ctypes.c_int32),
+        ("fwd_unstable", ctypes.c_int32),
         ("nsamples", ctypes.c_int64),
         ("ncoeffs", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64),
         ("max_kappa", ctypes.c_double),
         ("max_inv_residual", ctypes.c_double),
+        ("fwd_check_err", ctypes.c_double),
     ]
 
 
@@ -117,6 +122,7 @@ def lib():
         fn.restype = ctypes.c_int
     L.osht_batch_run.argtypes = [ctypes.POINTER(OshtJob), ctypes.c_int, vp, ctypes.POINTER(vp)]
     L.osht_graph_destroy.argtypes = [vp]
+    L.osht_plan_status.argtypes = [vp, i32p]
     L.osht_plan_set_profiling.argtypes = [vp, ctypes.c_int, ctypes.c_char_p]
     L.osht_plan_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]

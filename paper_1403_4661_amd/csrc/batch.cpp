@@ -64,6 +64,7 @@ void run_job(const osht_job_t& j, hipStream_t st) {
     case OSHT_DIR_FORWARD_ADJOINT: run_forward_adjoint(p, in, out, j.batch, st); break;
     default: throw Error{OSHT_EINVAL, "unknown job direction"};
   }
+  if (p.flags & OSHT_CHECK_FINITE) launch_finite_scan(p, out, 2 * (int64_t)p.L * p.L * j.batch, st);
 }
 
 // Issues every job: fork from `from`, plan-grouped streams, join into `from`.

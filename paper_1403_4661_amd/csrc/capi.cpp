@@ -90,18 +90,35 @@ struct DeviceGuard {
   }
 };
 
+// Forward-direction calls on a plan whose forward failed the plan-time
+// self-check (spin != 0 only) are refused unless the plan forces them.
+bool forward_refused(const Plan& p) { return p.fwd_unstable && !(p.flags & OSHT_SPIN_FWD_FORCE); }
+
+std::string refused_message(const Plan& p) {
+  char buf[256];
+  std::snprintf(buf, sizeof buf,
+                "the spin %d forward is unstable on this plan at L = %d (plan-time round trip error %.3g); "
+                "create the plan with OSHT_SPIN_FWD_FORCE to run it anyway",
+                p.spin, p.L, p.fwd_check_err);
+  return buf;
+}
+
 template <class Fn>
-int run_transform(const osht_plan_t* plan, const void* in, void* out, int64_t batch, Fn fn) {
+int run_transform(const osht_plan_t* plan, const void* in, void* out, int64_t batch, hipStream_t stream,
+                  bool forward_dir, Fn fn) {
   if (!plan) return fail(OSHT_EINVAL, "plan is NULL");
   if (!in || !out) return fail(OSHT_EINVAL, "input or output pointer is NULL");
   if (batch < 1 || batch > 65535) return fail(OSHT_EINVAL, "batch must be in [1, 65535]");
   Plan& p = const_cast<osht_plan_t*>(plan)->p;
   const size_t bytes = sizeof(double) * 2 * (size_t)p.L * p.L * (size_t)batch;
   if (overlaps(in, out, bytes)) return fail(OSHT_EINVAL, "input and output buffers overlap");
+  if (forward_dir && forward_refused(p)) return fail(OSHT_ENOTSUP, refused_message(p));
   try {
     std::lock_guard<std::mutex> lk(p.mu);
     DeviceGuard g(p.device);
     fn(p, static_cast<const double*>(in), static_cast<double*>(out));
+    if (p.flags & OSHT_CHECK_FINITE)
+      osht::launch_finite_scan(p, static_cast<const double*>(out), (int64_t)(bytes / sizeof(double)), stream);
   } catch (const Error& e) {
     return fail(e.code, e.msg);
   } catch (const std::bad_alloc&) {
@@ -113,7 +130,7 @@ int run_transform(const osht_plan_t* plan, const void* in, void* out, int64_t ba
 // As run_transform, with one side real (float64) and the other complex128.
 template <class Fn>
 int run_real_transform(const osht_plan_t* plan, const void* in, int64_t bin, bool in_cplx, void* out, int64_t bout,
-                       bool out_cplx, Fn fn) {
+                       bool out_cplx, hipStream_t stream, Fn fn) {
   if (!plan) return fail(OSHT_EINVAL, "plan is NULL");
   if (!in || !out) return fail(OSHT_EINVAL, "input or output pointer is NULL");
   if (bin < 1 || bin > 65535) return fail(OSHT_EINVAL, "batch must be in [1, 65535]");
@@ -129,6 +146,8 @@ int run_real_transform(const osht_plan_t* plan, const void* in, int64_t bin, boo
     std::lock_guard<std::mutex> lk(p.mu);
     DeviceGuard g(p.device);
     fn(p, static_cast<const double*>(in), static_cast<double*>(out));
+    if (p.flags & OSHT_CHECK_FINITE)
+      osht::launch_finite_scan(p, static_cast<const double*>(out), (int64_t)(ob / sizeof(double)), stream);
   } catch (const Error& e) {
     return fail(e.code, e.msg);
   } catch (const std::bad_alloc&) {
@@ -148,8 +167,9 @@ const char* osht_strerror(int code) {
     case OSHT_ENOMEM: return "out of memory";
     case OSHT_EHIP: return "HIP runtime error";
     case OSHT_ESINGULAR: return "a per-order system failed its inversion check";
-    case OSHT_ENOTSUP: return "unsupported flag combination";
+    case OSHT_ENOTSUP: return "not supported by this plan (flags or an unstable spin forward)";
     case OSHT_EIO: return "placement cache file unreadable or malformed";
+    case OSHT_ENONFINITE: return "a transform output held NaN or Inf";
     default: return "unknown error";
   }
 }
@@ -193,7 +213,8 @@ int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_di
   if (prec != OSHT_PREC_FP64 && prec != OSHT_PREC_FP32 && prec != OSHT_PREC_FP32_FWD)
     return fail(OSHT_ENOTSUP, "precision must be OSHT_PREC_FP64, OSHT_PREC_FP32 or OSHT_PREC_FP32_FWD");
   if (theta != OSHT_THETA_GREEDY && theta != OSHT_THETA_ALTERNATING) return fail(OSHT_EINVAL, "unknown placement flag");
-  if (flags & ~(OSHT_PREC_MASK | OSHT_THETA_MASK | OSHT_TUNE)) return fail(OSHT_EINVAL, "unknown flag bits");
+  if (flags & ~(OSHT_PREC_MASK | OSHT_THETA_MASK | OSHT_TUNE | OSHT_SPIN_FWD_FORCE | OSHT_CHECK_FINITE))
+    return fail(OSHT_EINVAL, "unknown flag bits");
   osht_plan_t* h = nullptr;
   try {
     h = new osht_plan_t;
@@ -256,6 +277,8 @@ int osht_plan_info(const osht_plan_t* plan, osht_info_t* out) {
   out->device_bytes = p.device_bytes();
   out->max_kappa = p.max_kappa;
   out->max_inv_residual = p.max_resid;
+  out->fwd_check_err = p.fwd_check_err;
+  out->fwd_unstable = p.fwd_unstable ? 1 : 0;
   return OSHT_OK;
 }
 
@@ -266,32 +289,32 @@ int osht_plan_theta(const osht_plan_t* plan, int32_t* numerators_host) {
 }
 
 int osht_inverse(const osht_plan_t* plan, const void* flm, void* f, int64_t batch, hipStream_t stream) {
-  return run_transform(plan, flm, f, batch,
+  return run_transform(plan, flm, f, batch, stream, false,
                        [&](Plan& p, const double* a, double* b) { osht::run_inverse(p, a, b, batch, stream); });
 }
 
 int osht_forward(const osht_plan_t* plan, const void* f, void* flm, int64_t batch, hipStream_t stream) {
-  return run_transform(plan, f, flm, batch,
+  return run_transform(plan, f, flm, batch, stream, true,
                        [&](Plan& p, const double* a, double* b) { osht::run_forward(p, a, b, batch, stream); });
 }
 
 int osht_forward_real(const osht_plan_t* plan, const void* f, void* flm, int64_t batch, hipStream_t stream) {
-  return run_real_transform(plan, f, batch, false, flm, batch, true,
+  return run_real_transform(plan, f, batch, false, flm, batch, true, stream,
                             [&](Plan& p, const double* a, double* b) { osht::run_forward_real(p, a, b, batch, stream); });
 }
 
 int osht_inverse_real(const osht_plan_t* plan, const void* flm, void* f, int64_t batch, hipStream_t stream) {
-  return run_real_transform(plan, flm, batch, true, f, batch, false,
+  return run_real_transform(plan, flm, batch, true, f, batch, false, stream,
                             [&](Plan& p, const double* a, double* b) { osht::run_inverse_real(p, a, b, batch, stream); });
 }
 
 int osht_inverse_adjoint(const osht_plan_t* plan, const void* f_bar, void* flm_bar, int64_t batch, hipStream_t stream) {
-  return run_transform(plan, f_bar, flm_bar, batch,
+  return run_transform(plan, f_bar, flm_bar, batch, stream, false,
                        [&](Plan& p, const double* a, double* b) { osht::run_inverse_adjoint(p, a, b, batch, stream); });
 }
 
 int osht_forward_adjoint(const osht_plan_t* plan, const void* flm_bar, void* f_bar, int64_t batch, hipStream_t stream) {
-  return run_transform(plan, flm_bar, f_bar, batch,
+  return run_transform(plan, flm_bar, f_bar, batch, stream, true,
                        [&](Plan& p, const double* a, double* b) { osht::run_forward_adjoint(p, a, b, batch, stream); });
 }
 
@@ -331,6 +354,26 @@ int osht_plan_kernel_time(osht_plan_t* plan, const char* name, int64_t* launches
   return OSHT_OK;
 }
 
+int osht_plan_status(osht_plan_t* plan, int32_t* status) {
+  if (!plan || !status) return fail(OSHT_EINVAL, "NULL argument");
+  Plan& p = plan->p;
+  *status = OSHT_OK;
+  if (!(p.flags & OSHT_CHECK_FINITE)) return OSHT_OK;
+  try {
+    std::lock_guard<std::mutex> lk(p.mu);
+    DeviceGuard g(p.device);
+    OSHT_HIP(hipDeviceSynchronize());
+    int32_t v = 0;
+    const int32_t zero = 0;
+    OSHT_HIP(hipMemcpy(&v, p.d_status.p, sizeof v, hipMemcpyDeviceToHost));
+    OSHT_HIP(hipMemcpy(p.d_status.p, &zero, sizeof zero, hipMemcpyHostToDevice));
+    if (v) *status = OSHT_ENONFINITE;
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  }
+  return OSHT_OK;
+}
+
 int osht_batch_run(const osht_job_t* jobs, int njobs, hipStream_t stream, osht_graph_t** graph_inout) {
   if (njobs < 0 || (njobs > 0 && !jobs)) return fail(OSHT_EINVAL, "bad job list");
   for (int i = 0; i < njobs; ++i) {
@@ -344,6 +387,8 @@ int osht_batch_run(const osht_job_t* jobs, int njobs, hipStream_t stream, osht_g
     for (int k = 0; k < i; ++k)
       if (jobs[k].plan == j.plan && jobs[k].batch != j.batch)
         return fail(OSHT_EINVAL, "jobs of one plan must share the batch size");
+    if ((j.direction == OSHT_DIR_FORWARD || j.direction == OSHT_DIR_FORWARD_ADJOINT) && forward_refused(j.plan->p))
+      return fail(OSHT_ENOTSUP, "job " + std::to_string(i) + ": " + refused_message(j.plan->p));
   }
   if (njobs == 0) return OSHT_OK;
   try {

@@ -173,6 +173,21 @@ struct FwdBlocks {
       d_w_ptr, d_w_col, d_w_val, d_wide_slot, d_wide_row, d_wt_ptr, d_wt_row, d_wt_val, d_minv, d_src_yrow;
 };
 
+// GEMM descriptors and task lists of the transforms for one batch size
+// (they hold workspace pointers and column counts).  Descriptor
+// d = dir * nslots + slot; tasks of all directions are kept in descriptor
+// order (d_gtask); the blocked forward and its adjoint have their own
+// per-block task lists (d_btask, d_atask).
+struct DescTables {
+  int64_t B = 0;
+  std::vector<GemmDesc> h_gdesc;
+  std::vector<GemmTask> h_gtask;
+  std::vector<int32_t> h_btask_ptr;   // per block: [fwd, corr, end) offsets into d_btask
+  std::vector<int32_t> h_atask_ptr;   // per block: [adjoint apply, adjoint corr, end) offsets into d_atask
+  DevBuf d_gdesc, d_gtask, d_btask, d_atask;
+  size_t bytes() const { return d_gdesc.bytes + d_gtask.bytes + d_btask.bytes + d_atask.bytes; }
+};
+
 struct Plan {
   int L = 0, spin = 0;
   uint32_t flags = 0;
@@ -183,6 +198,9 @@ struct Plan {
   std::string cache_dir;      // placement / tuning cache directory ("" = none)
   std::vector<Slot> slots;
   double max_kappa = 0.0, max_resid = 0.0;
+  double fwd_check_err = 0.0;  // plan-time FP64 round trip of one map (see osht_info_t)
+  bool fwd_unstable = false;   // spin != 0 and fwd_check_err above the stability bar
+  DevBuf d_status;             // OSHT_CHECK_FINITE: int32 set to 1 by a non-finite output
   // device memory
   DevBuf d_cos, d_sin, d_cosh, d_sinh;
   DevBuf d_slots;
@@ -196,15 +214,12 @@ struct Plan {
   // per-call workspace (grown on demand)
   DevBuf w_X, w_Y, w_H, w_T, w_D;
   FwdBlocks fb;
-  std::vector<int32_t> h_btask_ptr;   // per block: [fwd, corr, end) offsets into d_btask
-  DevBuf d_btask;
-  std::vector<int32_t> h_atask_ptr;   // per block: [adjoint apply, adjoint corr, end) offsets into d_atask
-  DevBuf d_atask;
-  DevBuf d_gdesc, d_gtask;    // GEMM descriptors for the transforms
-  int64_t ws_batch = 0;
-  int64_t ws_version = 0;     // bumped whenever workspace or descriptor tables change
-  std::vector<GemmDesc> h_gdesc;
-  std::vector<GemmTask> h_gtask;
+  // descriptor tables per batch size, for the current workspace (at most
+  // kMaxTables, least recently used evicted); `tab` is the last call's
+  std::vector<std::unique_ptr<DescTables>> tabs;
+  DescTables* tab = nullptr;
+  static constexpr int kMaxTables = 8;
+  int64_t ws_version = 0;     // bumped whenever workspace or descriptor tables are freed
   std::mutex mu;
   Profiler prof;
   int64_t device_bytes() const;
@@ -248,6 +263,19 @@ void run_inverse_real(Plan& p, const double* flm, double* f, int64_t B, hipStrea
 // Sizes the workspace and descriptor tables for batch B (synchronous; must
 // precede any graph capture of the transforms).
 void prepare_transforms(Plan& p, int64_t B);
+// Drops every descriptor table (after the device has drained), so that the
+// next call rebuilds them: needed when the forward blocks or the plan's
+// precision change.
+void invalidate_tables(Plan& p);
+// OSHT_CHECK_FINITE: scans n doubles for NaN / Inf, setting p.d_status.
+void launch_finite_scan(Plan& p, const double* x, int64_t n, hipStream_t st);
+// Plan-time FP64 round trip of one map; sets p.fwd_check_err and
+// p.fwd_unstable (spin != 0 plans above kSpinForwardStableErr).
+constexpr double kSpinForwardStableErr = 1e-8;
+// Largest |I - X_m P_m|_max of a usable forward: spin 0 plans above it are
+// refused (OSHT_ESINGULAR); spin != 0 plans above it get fwd_unstable.
+constexpr double kMaxInvResidual = 1e-10;
+void forward_self_check(Plan& p);
 // batch scheduler (batch.cpp); jobs validated by the caller
 void batch_run(const osht_job_t* jobs, int n, hipStream_t stream, osht_graph_t** graph_inout);
 

@@ -732,7 +732,7 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
   OSHT_HIP(hipFuncSetAttribute((const void*)delta_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 fb.lds_limit));
   const int nblk = (int)fb.q0.size();
-  const GemmTask* bt = p.d_btask.as<GemmTask>();
+  const GemmTask* bt = p.tab->d_btask.as<GemmTask>();
   for (int blk = 0; blk < nblk; ++blk) {
     const int ns = fb.slot_ptr[blk + 1] - fb.slot_ptr[blk];
     {
@@ -751,7 +751,7 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
         OSHT_HIP(hipGetLastError());
       }
     }
-    const int* tp = &p.h_btask_ptr[2 * blk];
+    const int* tp = &p.tab->h_btask_ptr[2 * blk];
     gemm_tasks_launch(p, bt + tp[0], tp[1] - tp[0], GemmRole::ApplyForward, "apply_forward", st);
     const int u0 = fb.unk_ptr[blk], nu = fb.unk_ptr[blk + 1] - u0;
     if (nu > 0) {
@@ -839,7 +839,7 @@ void tune_forward_blocks(Plan& p) {
         if (b > p.L) continue;
         p.fb.cpw = cpw;
         if (!fwd_blocks_fit(p, b) && b > 1) continue;
-        p.ws_batch = 0;
+        invalidate_tables(p);
         run_forward(p, in.as<double>(), out.as<double>(), Bt, 0);
         OSHT_HIP(hipEventRecord(e0, 0));
         for (int r = 0; r < 3; ++r) run_forward(p, in.as<double>(), out.as<double>(), Bt, 0);
@@ -871,7 +871,7 @@ void tune_forward_blocks(Plan& p) {
     int b = 32;
     while (!fwd_blocks_fit(p, b) && b > 1) b = std::max(1, b * 3 / 4);
   }
-  p.ws_batch = 0;
+  invalidate_tables(p);
   p.w_X.release();
   p.w_Y.release();
   p.w_H.release();
@@ -890,7 +890,7 @@ void run_forward_adjoint_blocked(Plan& p, const double* flmbar, double* fbar, in
   OSHT_HIP(hipFuncSetAttribute((const void*)eps_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 fb.lds_limit));
   const int nblk = (int)fb.q0.size();
-  const GemmTask* at = p.d_atask.as<GemmTask>();
+  const GemmTask* at = p.tab->d_atask.as<GemmTask>();
   double* H = p.w_H.as<double>();
   for (int blk = nblk - 1; blk >= 0; --blk) {  // ascending orders
     const int ns = fb.slot_ptr[blk + 1] - fb.slot_ptr[blk];
@@ -899,7 +899,7 @@ void run_forward_adjoint_blocked(Plan& p, const double* flmbar, double* fbar, in
     hipLaunchKernelGGL(fadj_block_gather_kernel, grid, dim3(256), 0, st, g, p.d_slots.as<Slot>(), sl, fb.q0[blk], flmbar,
                        H, p.w_X.as<double>());
     OSHT_HIP(hipGetLastError());
-    const int* tp = &p.h_atask_ptr[2 * blk];
+    const int* tp = &p.tab->h_atask_ptr[2 * blk];
     gemm_tasks_launch(p, at + tp[0], tp[1] - tp[0], GemmRole::Adjoint, "apply_forward_adjoint", st);
     const int u0 = fb.unk_ptr[blk], nu = fb.unk_ptr[blk + 1] - u0;
     if (nu > 0) {

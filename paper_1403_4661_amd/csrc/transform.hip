@@ -187,26 +187,48 @@ const char* const kApplyName[kNumDir] = {"apply_inverse",           "apply_forwa
                                          "apply_forward_correction", "apply_forward",
                                          "apply_forward_correction", "apply_forward_adjoint_correction"};
 
-// Workspace and GEMM descriptors for batch B (rebuilt when B or the buffers
-// change).  Descriptor d = dir * nslots + slot; tasks of all directions are
-// kept in descriptor order (d_gtask), and the blocked forward has its own
-// per-block task lists (d_btask) for its two GEMMs.
+// Workspace for batch B (grown on demand, never shrunk) and the GEMM
+// descriptor tables of B.  Tables are kept per batch size for the current
+// workspace, so that alternating batch sizes neither synchronise the device
+// nor rewrite tables that earlier, still running work may read; only a
+// workspace growth or an eviction (more than kMaxTables batch sizes) waits
+// for the device.
 void ensure_workspace(Plan& p, int64_t B) {
   const int64_t ncols = p.ncols_per_map * B;
   const size_t xy = sizeof(double) * (size_t)p.nslots * p.L * ncols;
   const size_t hb = sizeof(double) * 2 * (size_t)p.L * p.L * B;
   const size_t db = sizeof(double) * (size_t)p.nslots * std::max(p.fb.b, 1) * ncols;
   const bool grow = (xy > p.w_X.bytes) || (hb > p.w_H.bytes) || (db > p.w_D.bytes);
-  p.w_X.reserve(xy);
-  p.w_Y.reserve(xy);
-  p.w_H.reserve(hb);
-  p.w_D.reserve(db);
-  if (!grow && p.ws_batch == B && !p.h_gdesc.empty()) return;
-  // descriptor tables are rewritten below: earlier work on any stream may
-  // still read them
-  OSHT_HIP(hipDeviceSynchronize());
-  ++p.ws_version;
-  p.h_gdesc.clear();
+  if (grow) {
+    // the buffers and every table pointing into them are replaced: earlier
+    // work on any stream may still use them
+    OSHT_HIP(hipDeviceSynchronize());
+    p.tabs.clear();
+    p.tab = nullptr;
+    ++p.ws_version;
+    p.w_X.reserve(xy);
+    p.w_Y.reserve(xy);
+    p.w_H.reserve(hb);
+    p.w_D.reserve(db);
+  }
+  for (size_t i = 0; i < p.tabs.size(); ++i) {
+    if (p.tabs[i]->B == B) {
+      std::unique_ptr<DescTables> t = std::move(p.tabs[i]);  // most recently used last
+      p.tabs.erase(p.tabs.begin() + (long)i);
+      p.tabs.push_back(std::move(t));
+      p.tab = p.tabs.back().get();
+      return;
+    }
+  }
+  if ((int)p.tabs.size() >= Plan::kMaxTables) {
+    OSHT_HIP(hipDeviceSynchronize());
+    p.tabs.erase(p.tabs.begin());
+    ++p.ws_version;
+  }
+  p.tabs.push_back(std::unique_ptr<DescTables>(new DescTables));
+  DescTables& t = *p.tabs.back();
+  p.tab = &t;
+  t.B = B;
   double* X = p.w_X.as<double>();
   double* Y = p.w_Y.as<double>();
   double* D = p.w_D.as<double>();
@@ -284,58 +306,65 @@ void ensure_workspace(Plan& p, int64_t B) {
           d.alpha = -1.0; d.beta = 1.0;
         }
       }
-      p.h_gdesc.push_back(d);
+      t.h_gdesc.push_back(d);
     }
   }
-  gemm_tasks(p.h_gdesc, p.h_gtask);
-  upload(p.d_gdesc, p.h_gdesc);
-  upload(p.d_gtask, p.h_gtask);
+  gemm_tasks(t.h_gdesc, t.h_gtask);
+  upload(t.d_gdesc, t.h_gdesc);
+  upload(t.d_gtask, t.h_gtask);
   // per-block task lists of the blocked forward: [Q apply, correction]
   std::vector<GemmTask> bt;
-  p.h_btask_ptr.clear();
+  t.h_btask_ptr.clear();
   const int nblk = (int)p.fb.q0.size();
   auto emit = [&](int d) {
-    const GemmDesc& g = p.h_gdesc[d];
+    const GemmDesc& g = t.h_gdesc[d];
     if (g.K <= 0 || g.M <= g.m_lo) return;
     for (int a = g.m_lo / 64; a < (int)ceil_div(g.M, 64); ++a)
       for (int c = 0; c < (int)ceil_div(g.N, 64); ++c) bt.push_back(GemmTask{d, a, c, 0});
   };
   for (int blk = 0; blk < nblk; ++blk) {
     const bool has_unk = p.fb.unk_ptr[blk + 1] > p.fb.unk_ptr[blk];
-    p.h_btask_ptr.push_back((int32_t)bt.size());
+    t.h_btask_ptr.push_back((int32_t)bt.size());
     for (int dir : {kFwd, kFwdAlias})
       for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) emit(dir * p.nslots + p.fb.slot_list[i]);
-    p.h_btask_ptr.push_back((int32_t)bt.size());
+    t.h_btask_ptr.push_back((int32_t)bt.size());
     if (has_unk)
       for (int dir : {kCorr, kCorrAlias})
         for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) emit(dir * p.nslots + p.fb.slot_list[i]);
   }
-  p.h_btask_ptr.push_back((int32_t)bt.size());
-  upload(p.d_btask, bt);
+  t.h_btask_ptr.push_back((int32_t)bt.size());
+  upload(t.d_btask, bt);
   // per-block task lists of the blocked forward adjoint: [Q^T apply, correction]
   std::vector<GemmTask> at;
-  p.h_atask_ptr.clear();
+  t.h_atask_ptr.clear();
   auto emit_to = [&](std::vector<GemmTask>& v, int d) {
-    const GemmDesc& g = p.h_gdesc[d];
+    const GemmDesc& g = t.h_gdesc[d];
     if (g.K <= 0 || g.M <= g.m_lo) return;
     for (int a = g.m_lo / 64; a < (int)ceil_div(g.M, 64); ++a)
       for (int c = 0; c < (int)ceil_div(g.N, 64); ++c) v.push_back(GemmTask{d, a, c, 0});
   };
   for (int blk = 0; blk < nblk; ++blk) {
     const bool has_unk = p.fb.unk_ptr[blk + 1] > p.fb.unk_ptr[blk];
-    p.h_atask_ptr.push_back((int32_t)at.size());
+    t.h_atask_ptr.push_back((int32_t)at.size());
     for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i) emit_to(at, kFadj * p.nslots + p.fb.slot_list[i]);
-    p.h_atask_ptr.push_back((int32_t)at.size());
+    t.h_atask_ptr.push_back((int32_t)at.size());
     if (has_unk)
       for (int i = p.fb.slot_ptr[blk]; i < p.fb.slot_ptr[blk + 1]; ++i)
         emit_to(at, kFadjCorr * p.nslots + p.fb.slot_list[i]);
   }
-  p.h_atask_ptr.push_back((int32_t)at.size());
-  upload(p.d_atask, at);
-  p.ws_batch = B;
+  t.h_atask_ptr.push_back((int32_t)at.size());
+  upload(t.d_atask, at);
 }
 
 void prepare_transforms(Plan& p, int64_t B) { ensure_workspace(p, B); }
+
+void invalidate_tables(Plan& p) {
+  if (p.tabs.empty()) return;
+  OSHT_HIP(hipDeviceSynchronize());
+  p.tabs.clear();
+  p.tab = nullptr;
+  ++p.ws_version;
+}
 
 namespace {
 
@@ -467,11 +496,11 @@ void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, GemmRole rol
   if (count <= 0) return;
   if (p.prof.wants(prof_name)) {
     hipEvent_t e0 = p.prof.get(), e1 = p.prof.get();
-    launch_gemm(role, p.d_gdesc.as<GemmDesc>(), d_tasks, count, st, e0, e1);
+    launch_gemm(role, p.tab->d_gdesc.as<GemmDesc>(), d_tasks, count, st, e0, e1);
     p.prof.stat(prof_name).pending.emplace_back(e0, e1);
     return;
   }
-  launch_gemm(role, p.d_gdesc.as<GemmDesc>(), d_tasks, count, st);
+  launch_gemm(role, p.tab->d_gdesc.as<GemmDesc>(), d_tasks, count, st);
 }
 
 namespace {
@@ -479,15 +508,15 @@ namespace {
 // task range [first, count) of the GEMMs for direction dir, slots [s0, s1)
 void task_range(const Plan& p, int dir, int s0, int s1, int& first, int& count) {
   const int d0 = dir * p.nslots + s0, d1 = dir * p.nslots + s1;
-  int lo = 0, hi = (int)p.h_gtask.size();
+  int lo = 0, hi = (int)p.tab->h_gtask.size();
   {
     int a = 0, b = hi;
-    while (a < b) { int mid = (a + b) / 2; if (p.h_gtask[mid].desc < d0) a = mid + 1; else b = mid; }
+    while (a < b) { int mid = (a + b) / 2; if (p.tab->h_gtask[mid].desc < d0) a = mid + 1; else b = mid; }
     lo = a;
   }
   {
     int a = lo, b = hi;
-    while (a < b) { int mid = (a + b) / 2; if (p.h_gtask[mid].desc < d1) a = mid + 1; else b = mid; }
+    while (a < b) { int mid = (a + b) / 2; if (p.tab->h_gtask[mid].desc < d1) a = mid + 1; else b = mid; }
     hi = a;
   }
   first = lo;
@@ -502,7 +531,7 @@ void gemm_slots(Plan& p, int dir, int s0, int s1, hipStream_t st) {
                         : (dir == kFwd || dir == kFwdAlias)  ? GemmRole::ApplyForward
                         : (dir == kCorr || dir == kCorrAlias) ? GemmRole::Correction
                                                               : GemmRole::Adjoint;
-  gemm_tasks_launch(p, p.d_gtask.as<GemmTask>() + first, count, role, kApplyName[dir], st);
+  gemm_tasks_launch(p, p.tab->d_gtask.as<GemmTask>() + first, count, role, kApplyName[dir], st);
 }
 
 // slots of level am: spin 0 -> [am, am+1); spin s -> {-am, +am}
@@ -634,6 +663,71 @@ void run_forward_real(Plan& p, const double* f, double* flm, int64_t B, hipStrea
 void run_inverse_real(Plan& p, const double* flm, double* f, int64_t B, hipStream_t st) {
   check_real(p);
   run_inverse(p, flm, f, (B + 1) / 2, st, B);
+}
+
+// ---------------------------------------------------------------- checks
+namespace {
+
+// Any NaN / Inf among x[0, n) sets *flag (plain store: every writer writes 1).
+__global__ __launch_bounds__(256) void finite_scan_kernel(const double* __restrict__ x, int64_t n,
+                                                          int32_t* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[i]);
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) *flag = 1;
+}
+
+// splitmix64 (Steele, Lea & Flood, OOPSLA 2014): a fixed pseudo-random
+// stream for the self-check's input.
+uint64_t splitmix64(uint64_t& s) {
+  uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+void launch_finite_scan(Plan& p, const double* x, int64_t n, hipStream_t st) {
+  const unsigned blocks = (unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(n, 256 * 8), 1), 4096);
+  hipLaunchKernelGGL(finite_scan_kernel, dim3(blocks), dim3(256), 0, st, x, n, p.d_status.as<int32_t>());
+  OSHT_HIP(hipGetLastError());
+}
+
+// The forward is exact on band-limited samples, so forward(inverse(a)) - a
+// measures the rounding that the order-by-order chain of Procedure 1
+// amplifies on this plan.  Run in FP64 on one map with entries uniform in
+// [-1, 1) + i[-1, 1) (zero for l < |s|); synchronous, on the null stream.
+void forward_self_check(Plan& p) {
+  const int64_t n = (int64_t)p.L * p.L;
+  std::vector<double> a(2 * n), back(2 * n);
+  uint64_t seed = 0x5eed0000ull + (uint64_t)p.L * 131u + (uint64_t)(p.spin + 64);
+  const int as = std::abs(p.spin);
+  int l = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if ((int64_t)(l + 1) * (l + 1) <= i) ++l;  // i = l^2 + l + m
+    for (int part = 0; part < 2; ++part) {
+      const double u = (double)(splitmix64(seed) >> 11) * 0x1.0p-53;  // [0, 1)
+      a[2 * i + part] = l < as ? 0.0 : 2.0 * u - 1.0;
+    }
+  }
+  DevBuf d_a, d_f, d_g;
+  d_a.alloc(sizeof(double) * 2 * n);
+  d_f.alloc(sizeof(double) * 2 * n);
+  d_g.alloc(sizeof(double) * 2 * n);
+  OSHT_HIP(hipMemcpy(d_a.p, a.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice));
+  run_inverse(p, d_a.as<double>(), d_f.as<double>(), 1, 0);
+  run_forward(p, d_f.as<double>(), d_g.as<double>(), 1, 0);
+  OSHT_HIP(hipMemcpy(back.data(), d_g.p, sizeof(double) * 2 * n, hipMemcpyDeviceToHost));
+  double num = 0.0, den = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double dr = back[2 * i] - a[2 * i], di = back[2 * i + 1] - a[2 * i + 1];
+    const double d = std::sqrt(dr * dr + di * di);
+    num = (d == d && num == num) ? std::max(num, d) : NAN;
+    den = std::max(den, std::sqrt(a[2 * i] * a[2 * i] + a[2 * i + 1] * a[2 * i + 1]));
+  }
+  p.fwd_check_err = den > 0.0 ? num / den : num;
+  p.fwd_unstable = p.spin != 0 && !(p.fwd_check_err <= kSpinForwardStableErr && p.max_resid <= kMaxInvResidual);
 }
 
 }  // namespace osht

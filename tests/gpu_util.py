@@ -36,3 +36,18 @@ def relmax(a, b):
     b = np.asarray(b)
     den = np.max(np.abs(b))
     return float(np.max(np.abs(np.asarray(a) - b)) / (den if den > 0 else 1.0))
+
+
+def read_golden_values(name):
+    """(header dict, rows) of a tests/golden value file: '# key value' header
+    lines (max_abs is parsed as a float), then whitespace-separated rows whose
+    last two columns are the real and imaginary parts."""
+    head, rows = {}, []
+    for line in open(os.path.join(GOLDEN, name)):
+        if line.startswith("#"):
+            parts = line[1:].split()
+            if len(parts) == 2 and parts[0] == "max_abs":
+                head["max_abs"] = float(parts[1])
+            continue
+        rows.append(line.split())
+    return head, rows

@@ -33,13 +33,13 @@ def test_header_symbols_exported():
 
 def test_strerror_and_codes():
     L = _lib()
-    for code in (0, -1, -2, -3, -4, -5, -6):
-        assert L.osht_strerror(code)
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert L.osht_strerror(code) and L.osht_strerror(code) != b"unknown error"
     assert L.osht_strerror(-99) == b"unknown error"
 
 
 @pytest.mark.parametrize("L,spin,flags", [(0, 0, 0), (-3, 0, 0), (5000, 0, 0), (8, 8, 0), (8, -9, 0),
-                                          (8, 0, 0x200), (8, 0, 0x20)])
+                                          (8, 0, 0x800), (8, 0, 0x20), (8, 0, 0x1000)])
 def test_plan_create_rejects_bad_arguments(L, spin, flags):
     lib = _lib()
     h = ctypes.c_void_p()
@@ -59,6 +59,8 @@ def test_transforms_reject_null_plan_and_pointers():
         assert getattr(lib, fn)(None, ctypes.c_void_p(16), ctypes.c_void_p(4096), 1, None) == -1
     assert lib.osht_plan_destroy(None) == 0
     assert lib.osht_plan_info(None, None) == -1
+    st = ctypes.c_int32(5)
+    assert lib.osht_plan_status(None, ctypes.byref(st)) == -1
 
 
 def test_theta_rejects_bad_arguments():

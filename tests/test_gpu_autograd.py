@@ -8,13 +8,16 @@ dloss/dRe + i dloss/dIm (torch's), which for f = Y flm is 2 Y^H (f - target).
 Central finite differences with h = 1e-6 on the real and imaginary parts of
 32 entries (rng.choice after the draws) check it; the loss is quadratic, so
 the differences are exact up to rounding.  The adjoint kernels themselves are
-compared with the oracle's adjoints at L = 128, where the oracle is quick."""
+compared with the oracle's adjoints at L = 128, where the oracle is quick, and
+at L = 1024 on one map against oracle values stored at 1088 entries
+(tests/golden/iadj_L1024_seed3.txt, fadj_L1024_seed3.txt, written by
+tests/golden/make_parity_L1024.py from the oracle alone)."""
 
 import numpy as np
 import pytest
 
 from tests import inputs
-from tests.gpu_util import oracle_plan, relmax, to_dev, to_host
+from tests.gpu_util import oracle_plan, read_golden_values, relmax, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -92,3 +95,26 @@ def test_adjoints_vs_oracle_L128(s):
     if s == 0:
         y = inputs.coeffs(L, B, seed=7)
         assert relmax(to_host(plan.forward_adjoint(to_dev(y))), sht.forward_adjoint(op, y)) < 1e-10
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-6)])
+def test_adjoints_vs_oracle_L1024(precision, tol):
+    """Both adjoints at the differentiation workload's band-limit, one map:
+    inverse adjoint of N(0,1) samples and forward adjoint of (1+l)^-1
+    weighted coefficients (seed 3), against the stored oracle values.  The
+    FP32 plan's inverse adjoint reads FP32 A_m; its forward adjoint is FP64."""
+    from paper_1403_4661_amd import Plan
+
+    L = 1024
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((1, L * L)) + 1j * rng.standard_normal((1, L * L))
+    y = inputs.coeffs(L, 1, weighted=True, rng=rng)
+    plan = Plan(L, 0, precision=precision)
+    for name, fn, arg, t in (("iadj_L1024_seed3.txt", plan.inverse_adjoint, x, tol),
+                             ("fadj_L1024_seed3.txt", plan.forward_adjoint, y, 1e-11)):
+        head, rows = read_golden_values(name)
+        idx = np.asarray([int(r[0]) for r in rows])
+        ref = np.asarray([float(r[1]) + 1j * float(r[2]) for r in rows])
+        got = to_host(fn(to_dev(arg)))[0]
+        err = np.max(np.abs(got[idx] - ref)) / head["max_abs"]
+        assert err < t, (name, err)

@@ -7,19 +7,25 @@ seed 5 (the bench's input), one call per direction on the default plan
 - Inverse, every precision: rings 0, 1, 511, 512 and 1023 of maps 0 and 15
   against the oracle's ring-by-ring evaluation of the inverse definition
   (each ring on its own, from the per-order tables at that colatitude).
-- Forward: the oracle cannot give single coefficients without the whole
-  chain, so a property that holds at any size: the forward of band-limited
-  samples returns their coefficients.  The samples come from the FP64 plan's
-  inverse, itself pinned to the oracle above; the expected value is the
-  input flm.  FP64: <= 1e-11 (the method's FP64 floor for this input is
-  ~1.6e-12).  FP32 modes: <= 1e-6.
+- Forward against the oracle: map 0's samples are replaced by the oracle's
+  own inverse of map 0 (computed on the host, seconds), the batch of 16 is
+  transformed, and map 0's coefficients are compared with the oracle's
+  forward of the same samples at 1088 stored entries (every l < 8 plus 1024
+  seeded indices; tests/golden/forward_L1024_seed5.txt, written by
+  tests/golden/make_parity_L1024.py, which calls only the oracle).  Relative
+  to max |flm| over the whole output: FP64 <= 1e-11, FP32 modes <= 1e-6.
+- Forward, every map: the forward of band-limited samples returns their
+  coefficients (a property that holds at any size).  The samples come from
+  the FP64 plan's inverse, itself pinned to the oracle above; the expected
+  value is the input flm.  FP64: <= 1e-11 (the method's FP64 floor for this
+  input is ~1.6e-12).  FP32 modes: <= 1e-6.
 """
 
 import numpy as np
 import pytest
 
 from tests import inputs
-from tests.gpu_util import oracle_plan, relmax, to_dev, to_host
+from tests.gpu_util import oracle_plan, read_golden_values, relmax, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +82,27 @@ def test_headline_inverse_sampled_rings(precision):
     for k, v in ref.items():
         got = f[MAPS, k * k:k * k + 2 * k + 1]
         err = max(err, relmax(got, v))
+    assert err < TOL[precision], err
+
+
+def oracle_map0_samples():
+    """The oracle's inverse of map 0 (the input of the stored oracle forward)."""
+    if "f0" not in _cache:
+        from oracle import sht
+        _cache["f0"] = sht.inverse(oracle_plan(L), flm_host()[:1])
+    return _cache["f0"]
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_headline_forward_vs_oracle_map0(precision):
+    import torch
+    head, rows = read_golden_values("forward_L1024_seed5.txt")
+    idx = np.asarray([int(r[0]) for r in rows])
+    ref = np.asarray([float(r[1]) + 1j * float(r[2]) for r in rows])
+    f = fp64_samples().clone()
+    f[0] = torch.as_tensor(oracle_map0_samples()[0]).to(f.device)
+    g = to_host(plan(precision).forward(f))
+    err = np.max(np.abs(g[0, idx] - ref)) / head["max_abs"]
     assert err < TOL[precision], err
 
 

@@ -10,13 +10,24 @@ the checks are properties that hold at any size:
     3e-13 for 512 <= |m| < 1024, 5e-11 for 256 <= |m| < 512 and up to
     6e-5 for |m| < 256 (the FP64 oracle shows the same growth);
   * the FP32 plan (OSHT_PREC_FP32_FWD) agrees with the FP64 plan to 1e-6 in
-    both directions."""
+    both directions.
+Element by element against the oracle: map 0's samples on four rings --
+the ring nearest numerator 370 (theta ~ 0.284, where seeds of orders
+m ~ 560 underflow FP64 and the recursion rescales, Sec. III-F), the rings
+nearest both poles and every 8th sample of the equator -- against stored
+oracle values (tests/golden/inverse_L2048_s{0,2}_seed4.txt, written by
+tests/golden/make_parity_L2048.py from the oracle alone), relative to max
+|f| over those rings: FP64 <= 1e-11, FP32 <= 1e-6.
+Spin 2 (Sec. III-G), one plan at a time (a spin plan stores both signs of
+every order, ~140 GB in FP64): the inverse against the oracle as above; the
+forward's plan-time self-check flags the order-by-order chain as unstable
+(the method's, see the spin readings), so forward calls are refused."""
 
 import numpy as np
 import pytest
 
 from tests import inputs
-from tests.gpu_util import relmax, to_dev, to_host
+from tests.gpu_util import read_golden_values, relmax, to_dev, to_host
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -29,6 +40,22 @@ def _plan(prec):
     if prec not in _cache:
         _cache[prec] = Plan(L, 0, precision=prec)
     return _cache[prec]
+
+
+def _release(*keys):
+    import torch
+    for k in keys:
+        _cache.pop(k, None)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def _ring_error(f_map0, spin):
+    """max |GPU - oracle| / max |oracle| over the stored ring samples."""
+    head, rows = read_golden_values(f"inverse_L2048_s{spin}_seed4.txt")
+    pos = np.asarray([int(r[0]) ** 2 + int(r[1]) for r in rows])
+    ref = np.asarray([float(r[2]) + 1j * float(r[3]) for r in rows])
+    return float(np.max(np.abs(f_map0[pos] - ref)) / head["max_abs"])
 
 
 def _flm():
@@ -50,8 +77,10 @@ def test_L2048_fp64_pole_and_round_trip():
     # l ~ 2000 (the oracle's recursion agrees with 50-digit arithmetic to
     # that level at l = 2023); 2048 such terms are summed here
     assert np.max(np.abs(got - pole)) / np.max(np.abs(pole)) < 1e-10
+    fh = to_host(f)
+    assert _ring_error(fh[0], 0) < 1e-11
     back = to_host(p.forward(f))
-    _cache["f64"] = (to_host(f), back)
+    _cache["f64"] = (fh, back)
     mm = np.concatenate([np.arange(-k, k + 1) for k in range(L)])
     err = np.abs(back - flm) / np.max(np.abs(flm))
     assert err[:, np.abs(mm) >= 1024].max() < 1e-13
@@ -66,6 +95,7 @@ def test_L2048_fp32_matches_fp64():
     f64, back64 = _cache["f64"]
     flm = _flm()
     f32 = to_host(p32.inverse(to_dev(flm)))
+    assert _ring_error(f32[0], 0) < 1e-6
     assert relmax(f32, f64) < 1e-6
     # forward of the same FP64 samples: the FP32 coefficient rows add ~1e-8,
     # the FP64 alias chain is shared
@@ -73,5 +103,21 @@ def test_L2048_fp32_matches_fp64():
     assert relmax(g32, back64) < 1e-6
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32-fwd", 1e-6)])
+def test_L2048_spin2_inverse_vs_oracle_and_forward_flagged(prec, tol):
+    from paper_1403_4661_amd import OshtError, Plan
+    _release("fp64", "fp32-fwd", "f64", "spin")
+    p = _cache["spin"] = Plan(L, 2, precision=prec)
+    info = p.info()
+    assert info["fwd_unstable"] == 1
+    flm = inputs.coeffs(L, 2, seed=4, weighted=True, spin=2)
+    f = p.inverse(to_dev(flm))
+    assert _ring_error(to_host(f)[0], 2) < tol
+    with pytest.raises(OshtError) as e:
+        p.forward(f)
+    assert e.value.code == -5
+    _release("spin")
+
+
 def teardown_module(module):
-    _cache.clear()  # release the two L = 2048 plans (~150 GB of device memory)
+    _cache.clear()  # release the L = 2048 plans (up to ~150 GB of device memory)

@@ -13,10 +13,14 @@ _plans = {}
 
 
 def gpu_plan(L, s=0, placement="greedy"):
+    """Spin plans force their forward: these tests compare the kernels with
+    the oracle running the same order-by-order chain, also where the
+    plan-time self-check marks the chain unstable (tests/test_gpu_failure.py
+    covers that gate)."""
     from paper_1403_4661_amd import Plan
     key = (L, s, placement)
     if key not in _plans:
-        _plans[key] = Plan(L, s, placement=placement)
+        _plans[key] = Plan(L, s, placement=placement, force_spin_forward=s != 0)
     return _plans[key]
 
 
@@ -35,6 +39,7 @@ def test_plan_basics_L32():
     info = p.info()
     assert info["L"] == 32 and info["nsamples"] == 32 * 32 and info["ncoeffs"] == 32 * 32
     assert info["max_inv_residual"] < 1e-12
+    assert info["fwd_unstable"] == 0 and info["fwd_check_err"] < 1e-13
     assert p.theta_numerators() == golden_theta(32).tolist()
 
 
@@ -170,7 +175,7 @@ def test_forward_block_sizes(L, s, b, monkeypatch):
     from oracle import sht
     from paper_1403_4661_amd import Plan
     monkeypatch.setenv("OSHT_FWD_BLOCK", str(b))
-    p = Plan(L, s)
+    p = Plan(L, s, force_spin_forward=s != 0)
     flm = inputs.coeffs(L, 2, seed=L + b, spin=s)
     f = sht.inverse(oplan(L, s), flm)
     ref = sht.forward(oplan(L, s), f)
@@ -193,7 +198,7 @@ def test_forward_delta_paths(L, s, b, B, dense, monkeypatch):
     from paper_1403_4661_amd import Plan
     monkeypatch.setenv("OSHT_FWD_BLOCK", str(b))
     monkeypatch.setenv("OSHT_DELTA_DENSE", str(dense))
-    p = Plan(L, s)
+    p = Plan(L, s, force_spin_forward=s != 0)
     flm = inputs.coeffs(L, B, seed=L + 3 * b, spin=s)
     f = sht.inverse(oplan(L, s), flm)
     ref = sht.forward(oplan(L, s), f)
