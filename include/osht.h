@@ -61,6 +61,14 @@ extern "C" {
 #define OSHT_PREC_FP32_FWD    0x2u   /* OSHT_PREC_FP32, and the forward's coefficient rows P_m^{-1}
                                         also on FP32 matrix cores; its alias rows A_m^top P_m^{-1}
                                         stay FP64 */
+#define OSHT_PREC_I8X6        0x3u   /* inverse apply as exact int8 matrix-core products of 6-digit splits
+                                        of A_m (per-ring power-of-two scale) and of the coefficients
+                                        (per-column scale), digits of 7 bits: about 2e-10 relative to
+                                        max |f| (FP32 operands give ~1e-7), int32 accumulation, scaled and
+                                        summed in FP64; the forward as OSHT_PREC_FP32_FWD.  The inverse
+                                        adjoint reads FP64 A_m. */
+#define OSHT_PREC_I8X8        0x4u   /* as OSHT_PREC_I8X6 with 8 digits (~1e-14, FP64 grade) and the
+                                        forward in FP64 */
 #define OSHT_PREC_MASK        0x0fu
 /* colatitude placement (Sec. III-D) */
 #define OSHT_THETA_GREEDY       0x00u  /* condition-number-minimising greedy */

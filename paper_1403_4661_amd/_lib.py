@@ -23,6 +23,8 @@ OSHT_ENONFINITE = -7
 OSHT_PREC_FP64 = 0x0
 OSHT_PREC_FP32 = 0x1
 OSHT_PREC_FP32_FWD = 0x2
+OSHT_PREC_I8X6 = 0x3
+OSHT_PREC_I8X8 = 0x4
 OSHT_THETA_GREEDY = 0x00
 OSHT_THETA_ALTERNATING = 0x10
 OSHT_TUNE = 0x100

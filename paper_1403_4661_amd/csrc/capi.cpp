@@ -210,8 +210,9 @@ int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_di
   if (L < 1 || L > 4096) return fail(OSHT_EINVAL, "L must be in [1, 4096]");
   if (spin <= -L || spin >= L) return fail(OSHT_EINVAL, "|spin| must be < L");
   const uint32_t prec = flags & OSHT_PREC_MASK, theta = flags & OSHT_THETA_MASK;
-  if (prec != OSHT_PREC_FP64 && prec != OSHT_PREC_FP32 && prec != OSHT_PREC_FP32_FWD)
-    return fail(OSHT_ENOTSUP, "precision must be OSHT_PREC_FP64, OSHT_PREC_FP32 or OSHT_PREC_FP32_FWD");
+  if (prec != OSHT_PREC_FP64 && prec != OSHT_PREC_FP32 && prec != OSHT_PREC_FP32_FWD && prec != OSHT_PREC_I8X6 &&
+      prec != OSHT_PREC_I8X8)
+    return fail(OSHT_ENOTSUP, "precision must be OSHT_PREC_FP64, _FP32, _FP32_FWD, _I8X6 or _I8X8");
   if (theta != OSHT_THETA_GREEDY && theta != OSHT_THETA_ALTERNATING) return fail(OSHT_EINVAL, "unknown placement flag");
   if (flags & ~(OSHT_PREC_MASK | OSHT_THETA_MASK | OSHT_TUNE | OSHT_SPIN_FWD_FORCE | OSHT_CHECK_FINITE))
     return fail(OSHT_EINVAL, "unknown flag bits");
@@ -223,7 +224,8 @@ int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_di
     p.spin = spin;
     p.flags = flags;
     p.fp32 = prec == OSHT_PREC_FP32 || prec == OSHT_PREC_FP32_FWD;
-    p.fp32_fwd = prec == OSHT_PREC_FP32_FWD;
+    p.fp32_fwd = prec == OSHT_PREC_FP32_FWD || prec == OSHT_PREC_I8X6;
+    p.oz = prec == OSHT_PREC_I8X6 ? 6 : prec == OSHT_PREC_I8X8 ? 8 : 0;
     if (theta_cache_dir) p.cache_dir = theta_cache_dir;
     OSHT_HIP(hipGetDevice(&p.device));
     p.numer.assign(L, 0);

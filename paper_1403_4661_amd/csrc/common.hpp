@@ -102,6 +102,17 @@ struct GemmTask {
   int32_t desc, mt, nt, pad;
 };
 
+// Inverse apply on int8 digit splits (ozaki.hip): Y = A X for one slot.
+struct OzDesc {
+  const int8_t* A;     // digit plane 0 of A (row-major, leading dimension Kp); plane p at A + p * planeA
+  const int32_t* ea;   // row exponents
+  const int8_t* X;     // digit plane 0 of X (column-major, leading dimension ldX); plane q at X + q * planeX
+  const int32_t* xe;   // column exponents
+  double* C;           // Y (row-major, leading dimension ldc)
+  int64_t planeA, planeX;
+  int32_t M, N, Kp, ldX, ldc, pad;
+};
+
 // Ring DFT geometry: ring k has n = 2k+1 samples; Bluestein size M_k.
 struct RingDesc {
   int32_t n;      // 2k+1
@@ -185,7 +196,13 @@ struct DescTables {
   std::vector<int32_t> h_btask_ptr;   // per block: [fwd, corr, end) offsets into d_btask
   std::vector<int32_t> h_atask_ptr;   // per block: [adjoint apply, adjoint corr, end) offsets into d_atask
   DevBuf d_gdesc, d_gtask, d_btask, d_atask;
-  size_t bytes() const { return d_gdesc.bytes + d_gtask.bytes + d_btask.bytes + d_atask.bytes; }
+  // int8-digit plans: the inverse apply's descriptors and tasks
+  std::vector<OzDesc> h_oz;
+  std::vector<GemmTask> h_oztask;
+  DevBuf d_ozdesc, d_oztask;
+  size_t bytes() const {
+    return d_gdesc.bytes + d_gtask.bytes + d_btask.bytes + d_atask.bytes + d_ozdesc.bytes + d_oztask.bytes;
+  }
 };
 
 struct Plan {
@@ -207,7 +224,13 @@ struct Plan {
   DevBuf d_A, d_Q;            // FP64 blocks (FP32 plans release d_A and keep d_Q for the alias rows)
   DevBuf d_A32, d_Q32;        // FP32 copies, same element offsets (d_Q32 for OSHT_PREC_FP32_FWD only)
   bool fp32 = false;          // inverse-side applies on FP32 A_m (OSHT_PREC_FP32, OSHT_PREC_FP32_FWD)
-  bool fp32_fwd = false;      // forward coefficient rows on FP32 P_m^{-1} as well (OSHT_PREC_FP32_FWD)
+  bool fp32_fwd = false;      // forward coefficient rows on FP32 P_m^{-1} (OSHT_PREC_FP32_FWD, OSHT_PREC_I8X6)
+  // inverse apply on int8 digit splits of A_m and X_m (OSHT_PREC_I8X6 / _I8X8):
+  // the number of digits, 0 when off; d_A (FP64) stays for the adjoint
+  int oz = 0;
+  std::vector<int64_t> oz_offA8;  // byte offset of each slot's digit planes in d_A8
+  DevBuf d_A8, d_Aexp, d_ozoff;
+  DevBuf w_X8, w_Xexp;            // per-call digits and exponents of the right-hand sides
   DevBuf d_rings, d_chirp, d_twiddle, d_chirp_tab;
   std::vector<int32_t> h_ring_logM;
   int max_logM = 0;
@@ -269,6 +292,15 @@ void prepare_transforms(Plan& p, int64_t B);
 void invalidate_tables(Plan& p);
 // OSHT_CHECK_FINITE: scans n doubles for NaN / Inf, setting p.d_status.
 void launch_finite_scan(Plan& p, const double* x, int64_t n, hipStream_t st);
+// int8-digit inverse apply (ozaki.hip)
+void build_oz_planes(Plan& p);
+int oz_x_cols(const Plan& p, int64_t B);   // columns of the right-hand-side digit planes
+int oz_x_ld(const Plan& p);                // their leading dimension
+void oz_descs(const Plan& p, int64_t B, const double* Y, int8_t* X8, const int32_t* Xexp, std::vector<OzDesc>& descs,
+              std::vector<GemmTask>& tasks);
+void launch_oz_split_x(const Plan& p, const double* X, int64_t B, int8_t* X8, int32_t* Xexp, hipStream_t st);
+void launch_oz_apply(const Plan& p, const OzDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st,
+                     hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Plan-time FP64 round trip of one map; sets p.fwd_check_err and
 // p.fwd_unstable (spin != 0 plans above kSpinForwardStableErr).
 constexpr double kSpinForwardStableErr = 1e-8;

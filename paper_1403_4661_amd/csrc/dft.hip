@@ -29,6 +29,8 @@
 // remapped so that consecutive pairs stay on one XCD (one L2) -- the map
 // -fastest bin array H[(k^2 + q) B + b] is then written by nearby pairs.
 
+#include <algorithm>
+#include <array>
 #include <type_traits>
 
 #include "common.hpp"
@@ -218,9 +220,11 @@ struct PairCtx {
   bool active;
 };
 
-__device__ __forceinline__ PairCtx pair_of(const RingDesc* __restrict__ rings, int k0, int npairs, int B, int T) {
+// bid, G: the workgroup's index among the G workgroups of its size class
+__device__ __forceinline__ PairCtx pair_of(const RingDesc* __restrict__ rings, int k0, int npairs, int B, int T, int bid,
+                                           int G) {
   const int F = blockDim.x / T;
-  const int pair = xcd_remap(blockIdx.x, gridDim.x) * F + (int)(threadIdx.x / T);
+  const int pair = xcd_remap(bid, G) * F + (int)(threadIdx.x / T);
   PairCtx pc;
   pc.active = pair < npairs;
   const int pp = pc.active ? pair : 0;
@@ -243,7 +247,7 @@ __global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void chirp_kernel(const Rin
                                                                        cplx* __restrict__ table,
                                                                        const cplx* __restrict__ tw, int logMmax) {
   constexpr int logM = LOGM, M = 1 << LOGM, T = M / RPT;
-  const PairCtx pc = pair_of(rings, k0, nrings, 1, T);
+  const PairCtx pc = pair_of(rings, k0, nrings, 1, T, blockIdx.x, gridDim.x);
   const int t = threadIdx.x % T;
   FftCtx cx{lds_buf + (threadIdx.x / T) * (M + M / 16), tw, logM, logMmax, t, T};
   const cplx* w = chirp_tab + pc.base;
@@ -279,17 +283,42 @@ __device__ __forceinline__ void bluestein(cplx* v, const FftCtx& cx, const cplx*
   fft<true, LOGM>(v, cx);
 }
 
+struct RingArgs {
+  const RingDesc* rings;
+  const cplx* chirp_fft;
+  const cplx* chirp_tab;
+  const cplx* tw;
+  int logMmax, L, B, flag;  // flag: analysis normalises by 1/n, synthesis scales its input by 1/n
+  const cplx* in;           // f (analysis) or H (synthesis)
+  cplx* out;                // H (analysis) or f (synthesis)
+  double* freal;            // real-map samples (REAL variants)
+  int Breal;
+};
+
+// Size classes of one ring-DFT launch: workgroups [blk0[c], blk0[c] + nblk[c])
+// run the np[c] (ring, map) pairs of rings k0[c].. with FFT size 2^logM[c].
+// Every class starts at a multiple of 8 workgroups, so that its local
+// workgroup index keeps the XCD round-robin of the global one.
+constexpr int kMaxClasses = 12;
+struct ClassTab {
+  int n;
+  int blk0[kMaxClasses], nblk[kMaxClasses], k0[kMaxClasses], np[kMaxClasses], logM[kMaxClasses];
+};
+
 // samples f[b][L^2] -> bins H[(k^2 + q) * B + b] (scale 1/n or 1).
 template <int LOGM, bool REAL>
-__global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void ring_analysis_kernel(const RingDesc* __restrict__ rings, int k0,
-                                                            int npairs, const cplx* __restrict__ chirp_fft,
-                                                            const cplx* __restrict__ chirp_tab,
-                                                            const cplx* __restrict__ tw, int logMmax, int L,
-                                                            const cplx* __restrict__ f, cplx* __restrict__ H, int B,
-                                                            int normalise, const double* __restrict__ freal,
-                                                            int Breal) {
+__device__ __forceinline__ void analysis_body(const RingArgs& a, int k0, int npairs, int bid, int G) {
   constexpr int logM = LOGM, M = 1 << LOGM, T = M / RPT;
-  const PairCtx pc = pair_of(rings, k0, npairs, B, T);
+  if (xcd_remap(bid, G) * (int)(blockDim.x / T) >= npairs) return;  // a padding workgroup (uniform)
+  const RingDesc* __restrict__ rings = a.rings;
+  const cplx* __restrict__ chirp_fft = a.chirp_fft;
+  const cplx* __restrict__ chirp_tab = a.chirp_tab;
+  const cplx* __restrict__ tw = a.tw;
+  const cplx* __restrict__ f = a.in;
+  cplx* __restrict__ H = a.out;
+  const double* __restrict__ freal = a.freal;
+  const int logMmax = a.logMmax, L = a.L, B = a.B, normalise = a.flag, Breal = a.Breal;
+  const PairCtx pc = pair_of(rings, k0, npairs, B, T, bid, G);
   const int t = threadIdx.x % T;
   FftCtx cx{lds_buf + (threadIdx.x / T) * (M + M / 16), tw, logM, logMmax, t, T};
   const cplx* w = chirp_tab + pc.base;
@@ -374,15 +403,18 @@ __global__ __launch_bounds__(256) void fold_kernel(const YT* __restrict__ Y, cpl
 // Synthesis of (ring, map) pairs from the map-fastest bins H (optionally
 // times 1/n): f[b][k^2 + j] = sum_q H_k[q] e^{+2 pi i q j / n}.
 template <int LOGM, bool REAL>
-__global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void ring_synthesis_kernel(const RingDesc* __restrict__ rings, int k0,
-                                                             int npairs, const cplx* __restrict__ chirp_fft,
-                                                             const cplx* __restrict__ chirp_tab,
-                                                             const cplx* __restrict__ tw, int logMmax, int L,
-                                                             const cplx* __restrict__ H, int scale_inv_n,
-                                                             cplx* __restrict__ f, int B, double* __restrict__ freal,
-                                                             int Breal) {
+__device__ __forceinline__ void synthesis_body(const RingArgs& a, int k0, int npairs, int bid, int G) {
   constexpr int logM = LOGM, M = 1 << LOGM, T = M / RPT;
-  const PairCtx pc = pair_of(rings, k0, npairs, B, T);
+  if (xcd_remap(bid, G) * (int)(blockDim.x / T) >= npairs) return;  // a padding workgroup (uniform)
+  const RingDesc* __restrict__ rings = a.rings;
+  const cplx* __restrict__ chirp_fft = a.chirp_fft;
+  const cplx* __restrict__ chirp_tab = a.chirp_tab;
+  const cplx* __restrict__ tw = a.tw;
+  const cplx* __restrict__ H = a.in;
+  cplx* __restrict__ f = a.out;
+  double* __restrict__ freal = a.freal;
+  const int logMmax = a.logMmax, L = a.L, B = a.B, scale_inv_n = a.flag, Breal = a.Breal;
+  const PairCtx pc = pair_of(rings, k0, npairs, B, T, bid, G);
   const int t = threadIdx.x % T;
   FftCtx cx{lds_buf + (threadIdx.x / T) * (M + M / 16), tw, logM, logMmax, t, T};
   const cplx* w = chirp_tab + pc.base;
@@ -420,6 +452,41 @@ __global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void ring_synthesis_kernel(
       }
     }
   }
+}
+
+// Every size class of one direction in one launch of 256-thread workgroups
+// (FFT sizes up to 4096; the largest classes first, so the small ones fill
+// the tail): one launch instead of one per class, whose fixed cost
+// dominated the small classes.
+template <bool SYN, bool REAL>
+__global__ __launch_bounds__(256) void ring_dft_multi_kernel(RingArgs a, ClassTab ct) {
+  int c = 0;
+  while (c + 1 < ct.n && (int)blockIdx.x >= ct.blk0[c + 1]) ++c;
+  const int bid = (int)blockIdx.x - ct.blk0[c], G = ct.nblk[c];
+  auto run = [&](auto lg) {
+    constexpr int LG = decltype(lg)::value;
+    if constexpr (SYN) synthesis_body<LG, REAL>(a, ct.k0[c], ct.np[c], bid, G);
+    else analysis_body<LG, REAL>(a, ct.k0[c], ct.np[c], bid, G);
+  };
+  switch (ct.logM[c]) {
+    case 4: run(std::integral_constant<int, 4>{}); break;
+    case 5: run(std::integral_constant<int, 5>{}); break;
+    case 6: run(std::integral_constant<int, 6>{}); break;
+    case 7: run(std::integral_constant<int, 7>{}); break;
+    case 8: run(std::integral_constant<int, 8>{}); break;
+    case 9: run(std::integral_constant<int, 9>{}); break;
+    case 10: run(std::integral_constant<int, 10>{}); break;
+    case 11: run(std::integral_constant<int, 11>{}); break;
+    case 12: run(std::integral_constant<int, 12>{}); break;
+    default: break;
+  }
+}
+
+// 8192-point classes (L > 2048) take 512-thread workgroups of their own.
+template <bool SYN, bool REAL>
+__global__ __launch_bounds__(512) void ring_dft_8192_kernel(RingArgs a, int k0, int npairs) {
+  if constexpr (SYN) synthesis_body<13, REAL>(a, k0, npairs, blockIdx.x, gridDim.x);
+  else analysis_body<13, REAL>(a, k0, npairs, blockIdx.x, gridDim.x);
 }
 
 // tw[e] = e^{-2 pi i e / Mmax}; chirp_tab[k^2 + t] = e^{-i pi (t^2 mod 2n)/n},
@@ -535,25 +602,63 @@ void build_chirps(Plan& p) {
   });
 }
 
-void launch_ring_analysis(const Plan& p, const double* f, double* H, int64_t B, bool normalise, hipStream_t st,
-                          int64_t real_maps) {
-  for_each_class(p, [&](int k0, int k1, int logM) {
-    with_logM(logM, [&](auto lg) {
-      constexpr int LG = decltype(lg)::value;
-      const Shape sh = shape_for(LG);
-      const int np = (k1 - k0) * (int)B;
+namespace {
+
+// One direction of the ring DFTs: all size classes up to 4096 points in one
+// launch (largest first), 8192-point classes in launches of their own.
+void launch_ring_dft(const Plan& p, bool syn, const RingArgs& a, int64_t B, hipStream_t st) {
+  std::vector<std::array<int, 3>> cls;  // (logM, k0, k1)
+  for_each_class(p, [&](int k0, int k1, int logM) { cls.push_back({logM, k0, k1}); });
+  std::sort(cls.begin(), cls.end(), [](const std::array<int, 3>& x, const std::array<int, 3>& y) {
+    return x[0] > y[0];
+  });
+  ClassTab ct{};
+  int blk = 0;
+  size_t lds = 0;
+  const bool real = a.Breal > 0;
+  for (const auto& c : cls) {
+    const int logM = c[0], np = (c[2] - c[1]) * (int)B;
+    if (logM == 13) {
+      const Shape sh = shape_for(13);
       auto go = [&](auto kernel) {
         allow_lds((const void*)kernel, sh.lds);
-        hipLaunchKernelGGL(kernel, dim3((unsigned)ceil_div(np, sh.F)), dim3(sh.nthr), sh.lds, st,
-                           p.d_rings.as<RingDesc>(), k0, np, p.d_chirp.as<cplx>(), p.d_chirp_tab.as<cplx>(),
-                           p.d_twiddle.as<cplx>(), p.max_logM, p.L, reinterpret_cast<const cplx*>(f),
-                           reinterpret_cast<cplx*>(H), (int)B, normalise ? 1 : 0, f, (int)real_maps);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)ceil_div(np, sh.F)), dim3(sh.nthr), sh.lds, st, a, c[1], np);
         OSHT_HIP(hipGetLastError());
       };
-      if (real_maps > 0) go(ring_analysis_kernel<LG, true>);
-      else go(ring_analysis_kernel<LG, false>);
-    });
-  });
+      if (syn) real ? go(ring_dft_8192_kernel<true, true>) : go(ring_dft_8192_kernel<true, false>);
+      else real ? go(ring_dft_8192_kernel<false, true>) : go(ring_dft_8192_kernel<false, false>);
+      continue;
+    }
+    OSHT_CHECK(ct.n < kMaxClasses, OSHT_ENOTSUP, "too many ring FFT size classes");
+    const Shape sh = shape_for(logM);
+    const int nb = (int)ceil_div(ceil_div(np, sh.F), 8) * 8;
+    ct.blk0[ct.n] = blk;
+    ct.nblk[ct.n] = nb;
+    ct.k0[ct.n] = c[1];
+    ct.np[ct.n] = np;
+    ct.logM[ct.n] = logM;
+    ++ct.n;
+    blk += nb;
+    lds = std::max(lds, sh.lds);
+  }
+  if (ct.n == 0) return;
+  auto go = [&](auto kernel) {
+    allow_lds((const void*)kernel, lds);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blk), dim3(256), lds, st, a, ct);
+    OSHT_HIP(hipGetLastError());
+  };
+  if (syn) real ? go(ring_dft_multi_kernel<true, true>) : go(ring_dft_multi_kernel<true, false>);
+  else real ? go(ring_dft_multi_kernel<false, true>) : go(ring_dft_multi_kernel<false, false>);
+}
+
+}  // namespace
+
+void launch_ring_analysis(const Plan& p, const double* f, double* H, int64_t B, bool normalise, hipStream_t st,
+                          int64_t real_maps) {
+  const RingArgs a{p.d_rings.as<RingDesc>(), p.d_chirp.as<cplx>(), p.d_chirp_tab.as<cplx>(), p.d_twiddle.as<cplx>(),
+                   p.max_logM, p.L, (int)B, normalise ? 1 : 0, reinterpret_cast<const cplx*>(f),
+                   reinterpret_cast<cplx*>(H), const_cast<double*>(f), (int)real_maps};
+  launch_ring_dft(p, false, a, B, st);
 }
 
 void launch_fold(const Plan& p, const double* Y, double* H, int64_t B, hipStream_t st) {
@@ -569,23 +674,10 @@ void launch_fold(const Plan& p, const double* Y, double* H, int64_t B, hipStream
 
 void launch_ring_synthesis(const Plan& p, const double* H, int scale_inv_n, double* f, int64_t B, hipStream_t st,
                            int64_t real_maps) {
-  for_each_class(p, [&](int k0, int k1, int logM) {
-    with_logM(logM, [&](auto lg) {
-      constexpr int LG = decltype(lg)::value;
-      const Shape sh = shape_for(LG);
-      const int np = (k1 - k0) * (int)B;
-      auto go = [&](auto kernel) {
-        allow_lds((const void*)kernel, sh.lds);
-        hipLaunchKernelGGL(kernel, dim3((unsigned)ceil_div(np, sh.F)), dim3(sh.nthr), sh.lds, st,
-                           p.d_rings.as<RingDesc>(), k0, np, p.d_chirp.as<cplx>(), p.d_chirp_tab.as<cplx>(),
-                           p.d_twiddle.as<cplx>(), p.max_logM, p.L, reinterpret_cast<const cplx*>(H), scale_inv_n,
-                           reinterpret_cast<cplx*>(f), (int)B, f, (int)real_maps);
-        OSHT_HIP(hipGetLastError());
-      };
-      if (real_maps > 0) go(ring_synthesis_kernel<LG, true>);
-      else go(ring_synthesis_kernel<LG, false>);
-    });
-  });
+  const RingArgs a{p.d_rings.as<RingDesc>(), p.d_chirp.as<cplx>(), p.d_chirp_tab.as<cplx>(), p.d_twiddle.as<cplx>(),
+                   p.max_logM, p.L, (int)B, scale_inv_n, reinterpret_cast<const cplx*>(H),
+                   reinterpret_cast<cplx*>(f), f, (int)real_maps};
+  launch_ring_dft(p, true, a, B, st);
 }
 
 }  // namespace osht

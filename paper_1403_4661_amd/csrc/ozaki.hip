@@ -1,0 +1,418 @@
+// Inverse order-wise apply Y_m = A_m X_m as exact integer products of
+// int8 splits (the split-and-sum idea of Ozaki, Ogita, Oishi and Rump for
+// error-free matrix products, carried out on the int8 matrix cores).
+//
+// Each FP64 operand is written as a sum of S signed 7-bit digits under a
+// power-of-two scale: row i of A_m (ring i) with exponent e_i,
+//     A[i, k] = 2^{e_i} sum_{p<S} a_p[i, k] 2^{-7(p+1)} + O(2^{e_i - 7S}),
+// column c of X_m (one map, real or imaginary part, one sign of m) with
+// exponent f_c likewise (digits b_q), where |A[i, k]| < 2^{e_i} and the digits
+// come from repeated truncation: t = trunc(128 r), r <- 128 r - t (exact in
+// FP64), so every digit lies in [-127, 127].  The product keeps the digit
+// pairs p + q < S:
+//     Y[i, c] = 2^{e_i + f_c} sum_{d<S} 2^{-7(d+2)} D_d[i, c],
+//     D_d = sum_{p+q=d} a_p b_q   (int32: at most S * 127^2 * K < 2^31),
+// each D_d accumulated exactly by v_mfma_i32_16x16x64_i8 and scaled and
+// summed in FP64 at the end.  The error falls by about 2^7 per digit (CPU
+// emulation at L = 256: 2e-8 with 5 digits, 2e-10 with 6, 2e-12 with 7,
+// relative to max |f|); FP32 operands give 4e-8.
+//
+// Layouts.  A digits (plan): per slot, plane p at offA8 + p * Mp * Kp, row i
+// at i * Kp (k contiguous), Mp = L rounded up to 64, Kp = K rounded up to 64,
+// zero padded; e_i at Aexp[slot * Mp + i].  X digits (per call): per slot,
+// plane q at slot * S * Np * Kx + q * Np * Kx, column c at c * Kx, Np = the
+// slot columns rounded up to 64, Kx = L rounded up to 64; f_c at
+// Xexp[slot * Np + c].
+//
+// GEMM: one workgroup (4 waves) per 64 x 64 tile of Y; wave w owns rows
+// [16w, 16w + 16) and all 64 columns as four 16 x 16 blocks with S int32
+// accumulators each (one per digit sum d).  Per 64-deep k step, each lane
+// loads its 16-byte A chunk of every digit plane from HBM into registers
+// (one step ahead; every A byte is read once), and the workgroup loads the
+// step's B digits (S planes x 64 columns x 64 bytes, from L2) into a
+// double-buffered LDS tile.  MFMA operands: lane l supplies row (l % 16) of A
+// and column (l % 16) of B, digits k = 16 (l / 16) .. +15 of the step (any
+// k order shared by A and B gives the same sum); accumulator v of lane l
+// holds D[4 (l / 16) + v][l % 16].  LDS columns of 64 bytes hold their four
+// 16-byte chunks XOR-swizzled by (column / 4) % 4, so the 16 lanes of a k
+// group read 16 distinct bank quads.
+
+#include <climits>
+#include <cstdlib>
+
+#include "xform.hpp"
+
+namespace osht {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kOzTile = 64;
+
+template <int S>
+__device__ __forceinline__ void digits(double r, int8_t* out) {
+#pragma unroll
+  for (int p = 0; p < S; ++p) {
+    const double t = trunc(r * 128.0);
+    out[p] = (int8_t)(int)t;
+    r = r * 128.0 - t;
+  }
+}
+
+// exponent e with |v| < 2^e (0 for v = 0)
+__device__ __forceinline__ int exp_above(double v) {
+  int e = 0;
+  if (v != 0.0) (void)frexp(v, &e);
+  return e;
+}
+
+// Plan: A_m (FP64, column-major L x K, leading dimension ldA) -> digits.
+// One workgroup per (64-row tile, slot).  Thread t handles row t / 4 and,
+// in every 64 columns, the 16 columns 16 (t % 4) .. +15: it takes the row
+// maximum over them, then digits them and stores each plane's 16 bytes as
+// one vector, so four consecutive threads write 64 contiguous bytes.
+template <int S>
+__global__ __launch_bounds__(256) void oz_split_a_kernel(const Slot* __restrict__ slots, const double* __restrict__ A,
+                                                         int L, int Mp, const int64_t* __restrict__ offA8,
+                                                         int8_t* __restrict__ A8, int32_t* __restrict__ Aexp) {
+  __shared__ double red[64][4];
+  const int slot = blockIdx.y, m0 = blockIdx.x * 64;
+  const Slot sl = slots[slot];
+  const int Kp = (sl.K + 63) / 64 * 64;
+  const int t = threadIdx.x, row = t >> 2, j = t & 3;
+  const int r = m0 + row;
+  const double* Ac = A + sl.offA;
+  double mx = 0.0;
+  if (r < L) {
+    for (int k0 = 16 * j; k0 < sl.K; k0 += 64) {
+      double v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = k0 + i < sl.K ? fabs(Ac[r + (int64_t)(k0 + i) * sl.ldA]) : 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) mx = fmax(mx, v[i]);
+    }
+  }
+  red[row][j] = mx;
+  __syncthreads();
+  const int e = exp_above(fmax(fmax(red[row][0], red[row][1]), fmax(red[row][2], red[row][3])));
+  if (j == 0) Aexp[(int64_t)slot * Mp + r] = e;
+  int8_t* out = A8 + offA8[slot];
+  for (int k0 = 16 * j; k0 < Kp; k0 += 64) {
+    v4i w[S];
+#pragma unroll
+    for (int p = 0; p < S; ++p) w[p] = v4i{0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int k = k0 + i;
+      const double v = (r < L && k < sl.K) ? Ac[r + (int64_t)k * sl.ldA] : 0.0;
+      int8_t dg[S];
+      digits<S>(ldexp(v, -e), dg);
+#pragma unroll
+      for (int p = 0; p < S; ++p) w[p][i >> 2] |= (int)(uint8_t)dg[p] << (8 * (i & 3));
+    }
+#pragma unroll
+    for (int p = 0; p < S; ++p) *reinterpret_cast<v4i*>(out + (int64_t)p * Mp * Kp + (int64_t)r * Kp + k0) = w[p];
+  }
+}
+
+// Per call: slot-layout right-hand sides X[slot][row][col] (FP64, rows
+// l - l0 < K, ncols columns) -> per-column exponents and digits, in two
+// launches over (slot, 256-row chunk) workgroups: the column maxima of each
+// chunk (as exponents, combined by atomicMax into Xexp, which starts at
+// INT_MIN), then the digits.  Thread t handles column c0 + t / 4 and rows
+// 16 (t % 4) + 64 i .. +15 of the chunk; each plane's 16 bytes are stored as
+// one vector, so four consecutive threads write 64 contiguous bytes.
+constexpr int kSplitRows = 256;
+
+__global__ __launch_bounds__(256) void oz_fill_kernel(int32_t* __restrict__ x, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = v;
+}
+
+__global__ __launch_bounds__(256) void oz_colexp_kernel(const Slot* __restrict__ slots, const double* __restrict__ X,
+                                                        int L, int ncols, int Np, int32_t* __restrict__ Xexp) {
+  __shared__ double red[64][4];
+  const int slot = blockIdx.x, rc = blockIdx.y * kSplitRows;
+  const int K = slots[slot].K;
+  if (rc >= K) return;  // uniform
+  const int rend = min(K, rc + kSplitRows);
+  const int t = threadIdx.x, cl = t >> 2, j = t & 3;
+  const double* Xs = X + (int64_t)slot * L * ncols;
+  for (int c0 = 0; c0 < ncols; c0 += 64) {
+    const int c = c0 + cl;
+    double mx = 0.0;
+    if (c < ncols) {
+      for (int r0 = rc + 16 * j; r0 < rend; r0 += 64) {
+        double v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = r0 + i < rend ? fabs(Xs[(int64_t)(r0 + i) * ncols + c]) : 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) mx = fmax(mx, v[i]);
+      }
+    }
+    red[cl][j] = mx;
+    __syncthreads();
+    if (j == 0 && c < ncols) {
+      const double m = fmax(fmax(red[cl][0], red[cl][1]), fmax(red[cl][2], red[cl][3]));
+      if (m > 0.0) atomicMax(&Xexp[(int64_t)slot * Np + c], exp_above(m));
+    }
+    __syncthreads();  // red is rewritten by the next column chunk
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void oz_split_x_kernel(const Slot* __restrict__ slots, const double* __restrict__ X,
+                                                         int L, int ncols, int Np, int Kx, int8_t* __restrict__ X8,
+                                                         const int32_t* __restrict__ Xexp) {
+  const int slot = blockIdx.x, rc = blockIdx.y * kSplitRows;
+  const int K = slots[slot].K;
+  const int Kp = (K + 63) / 64 * 64;
+  if (rc >= Kp) return;  // uniform
+  const int rend = min(Kp, rc + kSplitRows);
+  const int t = threadIdx.x, cl = t >> 2, j = t & 3;
+  const double* Xs = X + (int64_t)slot * L * ncols;
+  int8_t* out = X8 + (int64_t)slot * S * Np * Kx;
+  for (int c0 = 0; c0 < Np; c0 += 64) {
+    const int c = c0 + cl;
+    int e = c < ncols ? Xexp[(int64_t)slot * Np + c] : 0;
+    if (e == INT_MIN) e = 0;  // an all-zero column
+    for (int r0 = rc + 16 * j; r0 < rend; r0 += 64) {
+      v4i w[S];
+#pragma unroll
+      for (int p = 0; p < S; ++p) w[p] = v4i{0, 0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int r = r0 + i;
+        const double v = (c < ncols && r < K) ? Xs[(int64_t)r * ncols + c] : 0.0;
+        int8_t dg[S];
+        digits<S>(ldexp(v, -e), dg);
+#pragma unroll
+        for (int p = 0; p < S; ++p) w[p][i >> 2] |= (int)(uint8_t)dg[p] << (8 * (i & 3));
+      }
+#pragma unroll
+      for (int p = 0; p < S; ++p)
+        *reinterpret_cast<v4i*>(out + (int64_t)p * Np * Kx + (int64_t)c * Kx + r0) = w[p];
+    }
+  }
+}
+
+// Global-memory views of descriptor pointers (plain pointers compile to flat
+// accesses, which also count in lgkmcnt and so would stall every LDS wait).
+typedef __attribute__((address_space(1))) const v4i* gv4i_ptr;
+typedef __attribute__((address_space(1))) const int32_t* gi32_ptr;
+typedef __attribute__((address_space(1))) double* gf64_ptr;
+
+template <int S>
+__device__ __forceinline__ void oz_load(gv4i_ptr src, int64_t plane, v4i* r) {
+#pragma unroll
+  for (int p = 0; p < S; ++p) r[p] = *(gv4i_ptr)((__attribute__((address_space(1))) const int8_t*)src + p * plane);
+}
+
+// All loads of the k loop go to registers (none straight to LDS): the
+// compiler then counts them in order and waits only for what each step
+// needs.  A: wave w loads its own 16 rows (each A byte is read once);
+// B: every thread loads one 16-byte chunk of one column per digit plane and
+// stores it to a double-buffered LDS tile, from which all four waves read.
+// PF: k steps of A held in flight per wave (registers), 1 or 2.
+template <int S, int PF>
+__global__ __launch_bounds__(256) void oz_apply_kernel(const OzDesc* __restrict__ descs,
+                                                       const GemmTask* __restrict__ tasks) {
+  __shared__ __align__(16) char bs[2][S][64 * 64];
+  // task order as in the streaming GEMM: runs of 16 consecutive tasks (the
+  // row tiles of one slot, which share its right-hand side) on one XCD
+  constexpr int C = 16, RND = 8 * C;
+  const int G = gridDim.x, bid = blockIdx.x, base = (bid / RND) * RND, pp = bid - base;
+  int ti;
+  if (base + RND <= G) {
+    ti = base + (pp & 7) * C + (pp >> 3);
+  } else {
+    const int Sz = G - base, q = Sz >> 3, r = Sz & 7, x = pp & 7, l = pp >> 3;
+    ti = base + (x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l);
+  }
+  const GemmTask tk = tasks[ti];
+  const OzDesc d = descs[tk.desc];
+  const int m0 = tk.mt * kOzTile, n0 = tk.nt * kOzTile;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  // this lane's A chunk: row m0 + 16 wave + li, bytes [16 kq, 16 kq + 16) of each 64-deep step
+  gv4i_ptr asrc = (gv4i_ptr)(d.A + (int64_t)(m0 + 16 * wave + li) * d.Kp + 16 * kq);
+  // this thread's B chunk: column n0 + (t >> 2), bytes [16 (t & 3), +16)
+  const int bc = t >> 2, bch = t & 3;
+  gv4i_ptr bsrc = (gv4i_ptr)(d.X + (int64_t)(n0 + bc) * d.ldX + 16 * bch);
+  const int bpos = bc * 64 + 16 * (bch ^ ((bc >> 2) & 3));
+  v4i acc[4][S];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int dd = 0; dd < S; ++dd) acc[cb][dd] = v4i{0, 0, 0, 0};
+  const int nk = d.Kp / 64;
+  v4i a[S], an[S], an2[S], an3[S], bt[S];
+  if (nk > 0) {
+    oz_load<S>(asrc, d.planeA, a);
+    if (PF >= 2) oz_load<S>(asrc + min(1, nk - 1) * 4, d.planeA, an);
+    if (PF >= 3) oz_load<S>(asrc + min(2, nk - 1) * 4, d.planeA, an2);
+    oz_load<S>(bsrc, d.planeX, bt);
+#pragma unroll
+    for (int p = 0; p < S; ++p) *reinterpret_cast<v4i*>(&bs[0][p][bpos]) = bt[p];
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    // A digits PF steps ahead and the next step's B digits (past the last
+    // step the last one is reloaded, so every path issues the same loads)
+    oz_load<S>(asrc + min(kt + PF, nk - 1) * 4, d.planeA, PF == 3 ? an3 : PF == 2 ? an2 : an);
+    oz_load<S>(bsrc + min(kt + 1, nk - 1) * 4, d.planeX, bt);
+    __syncthreads();  // B tile of step kt stored by every thread
+    const char* st = bs[kt & 1][0];
+    // B fragments of column block cb + 1 are read from LDS while the
+    // products of block cb run
+    v4i bf[2][S];
+    auto read_b = [&](int cb, v4i* dst) {
+      const int c = cb * 16 + li;
+      const int off = c * 64 + 16 * (kq ^ ((c >> 2) & 3));
+#pragma unroll
+      for (int q = 0; q < S; ++q) dst[q] = *reinterpret_cast<const v4i*>(st + q * 4096 + off);
+    };
+    read_b(0, bf[0]);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      if (cb + 1 < 4) read_b(cb + 1, bf[(cb + 1) & 1]);
+#pragma unroll
+      for (int q = 0; q < S; ++q)
+#pragma unroll
+        for (int p = 0; p + q < S; ++p)
+          acc[cb][p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[p], bf[cb & 1][q], acc[cb][p + q], 0, 0, 0);
+    }
+    // the other buffer was last read in step kt - 1, which every wave has
+    // finished (it passed this step's barrier)
+#pragma unroll
+    for (int p = 0; p < S; ++p) *reinterpret_cast<v4i*>(&bs[(kt + 1) & 1][p][bpos]) = bt[p];
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      a[p] = an[p];
+      if (PF >= 2) an[p] = an2[p];
+      if (PF >= 3) an2[p] = an3[p];
+    }
+  }
+  gi32_ptr ea = (gi32_ptr)d.ea;
+  gf64_ptr Cg = (gf64_ptr)d.C;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int col = n0 + cb * 16 + li;
+    if (col >= d.N) continue;
+    int fe = ((gi32_ptr)d.xe)[col];
+    if (fe == INT_MIN) fe = 0;  // an all-zero column (its digits and products are zero)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = m0 + 16 * wave + 4 * kq + v;
+      if (r < d.M) {
+        const int e = ea[r] + fe;
+        double y = 0.0;
+#pragma unroll
+        for (int dd = 0; dd < S; ++dd) y += ldexp((double)acc[cb][dd][v], e - 7 * (dd + 2));
+        Cg[(int64_t)r * d.ldc + col] = y;
+      }
+    }
+  }
+}
+
+// A prefetch depth (k steps held in registers per wave): two steps measured
+// no faster than one with 6 digits, and 8 digits have no registers to spare.
+template <int S> struct OzCfg { static constexpr int PF = 1; };
+
+template <int S>
+void oz_launch_apply(const OzDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st, hipEvent_t e0,
+                     hipEvent_t e1) {
+  const void* fn = (const void*)oz_apply_kernel<S, OzCfg<S>::PF>;
+  if (e0) {
+    void* args[] = {(void*)&d_desc, (void*)&d_task};
+    OSHT_HIP(hipExtLaunchKernel(fn, dim3(ntask), dim3(256), args, 0, st, e0, e1, 0));
+  } else {
+    hipLaunchKernelGGL((oz_apply_kernel<S, OzCfg<S>::PF>), dim3(ntask), dim3(256), 0, st, d_desc, d_task);
+  }
+  OSHT_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+int oz_x_cols(const Plan& p, int64_t B) { return (int)ceil_div(p.ncols_per_map * B, kOzTile) * kOzTile; }
+int oz_x_ld(const Plan& p) { return (int)ceil_div(p.L, kOzTile) * kOzTile; }
+
+void build_oz_planes(Plan& p) {
+  const int S = p.oz;
+  const int Mp = (int)ceil_div(p.L, kOzTile) * kOzTile;
+  std::vector<int64_t> off(p.nslots);
+  int64_t tot = 0;
+  for (int i = 0; i < p.nslots; ++i) {
+    off[i] = tot;
+    tot += (int64_t)S * Mp * (ceil_div(p.slots[i].K, kOzTile) * kOzTile);
+  }
+  p.oz_offA8 = off;
+  upload(p.d_ozoff, off);
+  p.d_A8.alloc((size_t)std::max<int64_t>(tot, 1));
+  p.d_Aexp.alloc(sizeof(int32_t) * (size_t)p.nslots * Mp);
+  const dim3 grid((unsigned)(Mp / kOzTile), (unsigned)p.nslots);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, grid, dim3(256), 0, 0, p.d_slots.as<Slot>(), p.d_A.as<double>(), p.L, Mp,
+                       p.d_ozoff.as<int64_t>(), p.d_A8.as<int8_t>(), p.d_Aexp.as<int32_t>());
+  };
+  if (S == 6) go(oz_split_a_kernel<6>);
+  else if (S == 8) go(oz_split_a_kernel<8>);
+  else throw Error{OSHT_ENOTSUP, "unsupported number of int8 digits"};
+  OSHT_HIP(hipGetLastError());
+  OSHT_HIP(hipDeviceSynchronize());
+}
+
+void oz_descs(const Plan& p, int64_t B, const double* Y, int8_t* X8, const int32_t* Xexp, std::vector<OzDesc>& descs,
+              std::vector<GemmTask>& tasks) {
+  const int S = p.oz;
+  const int Mp = (int)ceil_div(p.L, kOzTile) * kOzTile;
+  const int ncols = p.ncols_per_map * (int)B, Np = oz_x_cols(p, B), Kx = oz_x_ld(p);
+  descs.clear();
+  tasks.clear();
+  for (int i = 0; i < p.nslots; ++i) {
+    const Slot& sl = p.slots[i];
+    OzDesc d{};
+    const int Kp = (int)ceil_div(sl.K, kOzTile) * kOzTile;
+    d.A = p.d_A8.as<int8_t>() + p.oz_offA8[i];
+    d.ea = p.d_Aexp.as<int32_t>() + (int64_t)i * Mp;
+    d.X = X8 + (int64_t)i * S * Np * Kx;
+    d.xe = Xexp + (int64_t)i * Np;
+    d.C = const_cast<double*>(Y) + (int64_t)i * p.L * ncols;
+    d.planeA = (int64_t)Mp * Kp;
+    d.planeX = (int64_t)Np * Kx;
+    d.M = p.L;
+    d.N = ncols;
+    d.Kp = Kp;
+    d.ldX = Kx;
+    d.ldc = ncols;
+    descs.push_back(d);
+    for (int a = 0; a < Mp / kOzTile; ++a)
+      for (int c = 0; c < Np / kOzTile; ++c) tasks.push_back(GemmTask{i, a, c, 0});
+  }
+}
+
+void launch_oz_split_x(const Plan& p, const double* X, int64_t B, int8_t* X8, int32_t* Xexp, hipStream_t st) {
+  const int ncols = p.ncols_per_map * (int)B, Np = oz_x_cols(p, B), Kx = oz_x_ld(p);
+  const int64_t ne = (int64_t)p.nslots * Np;
+  hipLaunchKernelGGL(oz_fill_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(ne, 256), 1024)), dim3(256), 0, st, Xexp,
+                     ne, (int32_t)INT_MIN);
+  OSHT_HIP(hipGetLastError());
+  const dim3 grid((unsigned)p.nslots, (unsigned)ceil_div(Kx, kSplitRows));
+  hipLaunchKernelGGL(oz_colexp_kernel, grid, dim3(256), 0, st, p.d_slots.as<Slot>(), X, p.L, ncols, Np, Xexp);
+  OSHT_HIP(hipGetLastError());
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, p.d_slots.as<Slot>(), X, p.L, ncols, Np, Kx, X8,
+                       static_cast<const int32_t*>(Xexp));
+  };
+  if (p.oz == 6) go(oz_split_x_kernel<6>);
+  else go(oz_split_x_kernel<8>);
+  OSHT_HIP(hipGetLastError());
+}
+
+void launch_oz_apply(const Plan& p, const OzDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st,
+                     hipEvent_t e0, hipEvent_t e1) {
+  if (ntask <= 0) return;
+  if (p.oz == 6) oz_launch_apply<6>(d_desc, d_task, ntask, st, e0, e1);
+  else oz_launch_apply<8>(d_desc, d_task, ntask, st, e0, e1);
+}
+
+}  // namespace osht

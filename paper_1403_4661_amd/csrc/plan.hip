@@ -377,7 +377,7 @@ __global__ void narrow_kernel(const double* __restrict__ src, float* __restrict_
 int64_t Plan::device_bytes() const {
   size_t n = 0;
   for (const DevBuf* b : {&d_cos, &d_sin, &d_cosh, &d_sinh, &d_slots, &d_A, &d_Q, &d_A32, &d_Q32, &d_rings, &d_chirp,
-                          &d_twiddle, &d_chirp_tab, &w_X, &w_Y, &w_H, &w_T, &w_D, &d_status,
+                          &d_twiddle, &d_chirp_tab, &w_X, &w_Y, &w_H, &w_T, &w_D, &d_status, &d_A8, &d_Aexp, &d_ozoff, &w_X8, &w_Xexp,
                           &fb.d_slot_list, &fb.d_lev_ptr, &fb.d_unk_slot, &fb.d_unk_r, &fb.d_unk_m, &fb.d_src_ptr,
                           &fb.d_src_slot, &fb.d_src_row, &fb.d_src_m, &fb.d_w_ptr, &fb.d_w_col, &fb.d_w_val,
                           &fb.d_wide_slot, &fb.d_wide_row, &fb.d_wt_ptr, &fb.d_wt_row, &fb.d_wt_val, &fb.d_minv,
@@ -502,33 +502,35 @@ void build_plan(Plan& p) {
   // the forward self-check runs in FP64, before the FP32 copies replace A_m
   {
     const bool f32 = p.fp32, f32q = p.fp32_fwd;
+    const int oz = p.oz;
     p.fp32 = p.fp32_fwd = false;
+    p.oz = 0;
     forward_self_check(p);
     invalidate_tables(p);
     p.fp32 = f32;
     p.fp32_fwd = f32q;
+    p.oz = oz;
   }
+  if (p.oz) build_oz_planes(p);
   if (p.flags & OSHT_CHECK_FINITE) {
     p.d_status.alloc(sizeof(int32_t));
     OSHT_HIP(hipMemset(p.d_status.p, 0, sizeof(int32_t)));
   }
-  if (p.fp32) {
-    // FP32 copies at the same element offsets.  A_m is released; Q_m stays
-    // in FP64 (the forward's alias rows A_m^top P_m^{-1} and the forward
-    // adjoint always use it), with an FP32 copy for the coefficient rows
-    // under OSHT_PREC_FP32_FWD
-    auto narrow = [](DevBuf& src, DevBuf& dst, bool release) {
-      const int64_t n = (int64_t)(src.bytes / sizeof(double));
-      dst.alloc(sizeof(float) * std::max<int64_t>(n, 1));
-      hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(n, 256), 1), 8192)),
-                         dim3(256), 0, 0, src.as<double>(), dst.as<float>(), n);
-      OSHT_HIP(hipGetLastError());
-      OSHT_HIP(hipDeviceSynchronize());
-      if (release) src.release();
-    };
-    narrow(p.d_A, p.d_A32, true);
-    if (p.fp32_fwd) narrow(p.d_Q, p.d_Q32, false);
-  }
+  // FP32 copies at the same element offsets.  FP32 plans release A_m; Q_m
+  // stays in FP64 (the forward's alias rows A_m^top P_m^{-1} and the forward
+  // adjoint always use it), with an FP32 copy for the coefficient rows when
+  // the forward's coefficient tiles run in FP32
+  auto narrow = [](DevBuf& src, DevBuf& dst, bool release) {
+    const int64_t n = (int64_t)(src.bytes / sizeof(double));
+    dst.alloc(sizeof(float) * std::max<int64_t>(n, 1));
+    hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(n, 256), 1), 8192)),
+                       dim3(256), 0, 0, src.as<double>(), dst.as<float>(), n);
+    OSHT_HIP(hipGetLastError());
+    OSHT_HIP(hipDeviceSynchronize());
+    if (release) src.release();
+  };
+  if (p.fp32) narrow(p.d_A, p.d_A32, true);
+  if (p.fp32_fwd) narrow(p.d_Q, p.d_Q32, false);
   if ((p.flags & OSHT_TUNE) && !env) tune_forward_blocks(p);
   OSHT_HIP(hipDeviceSynchronize());
 }

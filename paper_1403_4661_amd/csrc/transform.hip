@@ -198,7 +198,11 @@ void ensure_workspace(Plan& p, int64_t B) {
   const size_t xy = sizeof(double) * (size_t)p.nslots * p.L * ncols;
   const size_t hb = sizeof(double) * 2 * (size_t)p.L * p.L * B;
   const size_t db = sizeof(double) * (size_t)p.nslots * std::max(p.fb.b, 1) * ncols;
-  const bool grow = (xy > p.w_X.bytes) || (hb > p.w_H.bytes) || (db > p.w_D.bytes);
+  // int8-digit plans: digit planes and exponents of the right-hand sides
+  const size_t x8 = p.oz ? (size_t)p.nslots * p.oz * oz_x_cols(p, B) * (size_t)oz_x_ld(p) : 0;
+  const size_t xe = p.oz ? sizeof(int32_t) * (size_t)p.nslots * oz_x_cols(p, B) : 0;
+  const bool grow = (xy > p.w_X.bytes) || (hb > p.w_H.bytes) || (db > p.w_D.bytes) || (x8 > p.w_X8.bytes) ||
+                    (xe > p.w_Xexp.bytes);
   if (grow) {
     // the buffers and every table pointing into them are replaced: earlier
     // work on any stream may still use them
@@ -210,6 +214,8 @@ void ensure_workspace(Plan& p, int64_t B) {
     p.w_Y.reserve(xy);
     p.w_H.reserve(hb);
     p.w_D.reserve(db);
+    p.w_X8.reserve(x8);
+    p.w_Xexp.reserve(xe);
   }
   for (size_t i = 0; i < p.tabs.size(); ++i) {
     if (p.tabs[i]->B == B) {
@@ -312,6 +318,11 @@ void ensure_workspace(Plan& p, int64_t B) {
   gemm_tasks(t.h_gdesc, t.h_gtask);
   upload(t.d_gdesc, t.h_gdesc);
   upload(t.d_gtask, t.h_gtask);
+  if (p.oz) {
+    oz_descs(p, B, Y, p.w_X8.as<int8_t>(), p.w_Xexp.as<int32_t>(), t.h_oz, t.h_oztask);
+    upload(t.d_ozdesc, t.h_oz);
+    upload(t.d_oztask, t.h_oztask);
+  }
   // per-block task lists of the blocked forward: [Q apply, correction]
   std::vector<GemmTask> bt;
   t.h_btask_ptr.clear();
@@ -549,7 +560,21 @@ void run_inverse(Plan& p, const double* flm, double* f, int64_t B, hipStream_t s
   const Geo g = geo(p, B);
   (void)g;
   launch_coef_to_slots(p, flm, p.w_X.as<double>(), B, st, p.fp32, real_maps);
-  gemm_slots(p, kInv, 0, p.nslots, st);
+  if (p.oz) {
+    launch_oz_split_x(p, p.w_X.as<double>(), B, p.w_X8.as<int8_t>(), p.w_Xexp.as<int32_t>(), st);
+    const int n = (int)p.tab->h_oztask.size();
+    const OzDesc* dd = p.tab->d_ozdesc.as<OzDesc>();
+    const GemmTask* dt = p.tab->d_oztask.as<GemmTask>();
+    if (p.prof.wants(kApplyName[kInv])) {
+      hipEvent_t e0 = p.prof.get(), e1 = p.prof.get();
+      launch_oz_apply(p, dd, dt, n, st, e0, e1);
+      p.prof.stat(kApplyName[kInv]).pending.emplace_back(e0, e1);
+    } else {
+      launch_oz_apply(p, dd, dt, n, st);
+    }
+  } else {
+    gemm_slots(p, kInv, 0, p.nslots, st);
+  }
   {
     ProfScope ps(p.prof, "fold", st);
     launch_fold(p, p.w_Y.as<double>(), p.w_H.as<double>(), B, st);

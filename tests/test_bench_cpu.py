@@ -47,14 +47,22 @@ def test_apply_peak_is_harmonic_blend():
     assert bench.apply_peak("mixed", f32, f64) == pytest.approx(115.25, abs=0.01)
 
 
-def test_traffic_record_is_keyed_to_workload():
-    """The committed traffic figure is reported only for the path, size and
-    launch count it was measured on (and, checked inside, the current sources)."""
+def test_traffic_record_is_keyed_to_workload(tmp_path, monkeypatch):
+    """A traffic record is reported only for the path, size, launch count and
+    kernel sources it was measured on."""
     import bench
+    rec = tmp_path / "rec.md"
+    rec.write_text("# record\n\n- `path`: `fp64`\n- `L`: `1024`\n- `batch`: `16`\n- `launches_per_step`: `22`\n"
+                   "- `traffic_bytes_per_launch`: `1.5e+08`\n"
+                   f"- `sources_sha256`: `{bench.sources_sha256()}`\n")
+    monkeypatch.setattr(bench, "traffic_file", lambda path: str(rec) if path == "fp64" else str(tmp_path / "none.md"))
+    assert bench.measured_traffic("fp64", 1024, 16, 22) == 1.5e8
+    assert bench.measured_traffic("mixed", 1024, 16, 22) is None
+    assert bench.measured_traffic("fp64", 512, 16, 22) is None
+    assert bench.measured_traffic("fp64", 1024, 8, 22) is None
+    assert bench.measured_traffic("fp64", 1024, 16, 21) is None
+    rec.write_text(rec.read_text().replace(bench.sources_sha256(), "0" * 64))
     assert bench.measured_traffic("fp64", 1024, 16, 22) is None
-    assert bench.measured_traffic("mixed", 512, 16, 22) is None
-    assert bench.measured_traffic("mixed", 1024, 8, 22) is None
-    assert bench.measured_traffic("mixed", 1024, 16, 21) is None
 
 
 def test_more_than_one_gpu_is_refused():

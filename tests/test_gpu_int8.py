@@ -1,0 +1,96 @@
+"""The inverse apply on int8 digit splits (OSHT_PREC_I8X6 / _I8X8): A_m and
+the coefficients are written as 6 or 8 signed 7-bit digits under
+power-of-two scales, the digit products are accumulated exactly by the int8
+matrix cores, and the scaled sums are added in FP64.
+
+Against the FP64 oracle, element by element (relative to max |f| of the
+call): 6 digits <= 1e-8 (the split's error falls about 2^7 per digit; CPU
+emulation gives 2e-10 at L = 256), 8 digits <= 1e-11 (the FP64 bar).  The
+forward of an I8X6 plan runs the FP32_FWD forward (<= 1e-6), of an I8X8 plan
+the FP64 one (<= 1e-11); the inverse adjoint reads FP64 A_m (<= 1e-12).
+Shapes: tiny and ragged band-limits (tails of the 64-row, 64-column and
+64-deep tiles), batches that leave the column tile partly empty, spin +-2
+and -1 (both signs of m in their own slots), and bit-for-bit repeatability.
+"""
+
+import numpy as np
+import pytest
+
+from tests import inputs
+from tests.gpu_util import oracle_plan, relmax, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL_INV = {"i8x6": 1e-8, "i8x8": 1e-11}
+TOL_FWD = {"i8x6": 1e-6, "i8x8": 1e-11}
+_plans, _oplans = {}, {}
+
+
+def plan(L, s, precision):
+    from paper_1403_4661_amd import Plan
+    key = (L, s, precision)
+    if key not in _plans:
+        _plans[key] = Plan(L, s, precision=precision, force_spin_forward=s != 0)
+    return _plans[key]
+
+
+def oplan(L, s=0):
+    if (L, s) not in _oplans:
+        _oplans[(L, s)] = oracle_plan(L, s)
+    return _oplans[(L, s)]
+
+
+CASES = [(1, 1, 0, False, 1), (2, 2, 0, False, 2), (33, 3, 0, False, 3), (65, 2, 0, False, 4),
+         (100, 17, 0, True, 5), (130, 5, 0, True, 6), (16, 2, 2, False, 7), (21, 1, -1, False, 8),
+         (40, 3, -2, True, 9)]
+
+
+@pytest.mark.parametrize("precision", ["i8x6", "i8x8"])
+@pytest.mark.parametrize("L,B,s,weighted,seed", CASES)
+def test_int8_inverse_matches_oracle(L, B, s, weighted, seed, precision):
+    from oracle import sht
+    flm = inputs.coeffs(L, B, seed=seed, weighted=weighted, spin=s)
+    got = to_host(plan(L, s, precision).inverse(to_dev(flm)))
+    assert relmax(got, sht.inverse(oplan(L, s), flm)) < TOL_INV[precision]
+
+
+@pytest.mark.parametrize("precision", ["i8x6", "i8x8"])
+@pytest.mark.parametrize("L,B,weighted,seed", [(33, 3, False, 3), (100, 17, True, 5)])
+def test_int8_plan_forward_and_adjoint(L, B, weighted, seed, precision):
+    from oracle import sht
+    op = oplan(L)
+    flm = inputs.coeffs(L, B, seed=seed, weighted=weighted)
+    f = sht.inverse(op, flm)
+    p = plan(L, 0, precision)
+    assert relmax(to_host(p.forward(to_dev(f))), sht.forward(op, f)) < TOL_FWD[precision]
+    assert relmax(to_host(p.inverse_adjoint(to_dev(f))), sht.inverse_adjoint(op, f)) < 1e-12
+
+
+def test_int8_inverse_repeatable_and_zero_maps():
+    """Fixed reduction order: repeated calls agree bit for bit; an all-zero
+    map (exponent of an empty column) gives exact zeros beside a nonzero map."""
+    import torch
+    p = plan(65, 0, "i8x6")
+    flm = inputs.coeffs(65, 3, seed=11)
+    flm[1] = 0.0
+    x = to_dev(flm)
+    a, b = to_host(p.inverse(x)), to_host(p.inverse(x))
+    assert np.array_equal(a, b)
+    assert np.all(a[1] == 0.0)
+    assert relmax(a[[0, 2]], __import__("oracle").sht.inverse(oplan(65), flm[[0, 2]])) < TOL_INV["i8x6"]
+
+
+def test_int8_round_trip_headline_size():
+    """L = 1024, batch 16, headline input: inverse then forward on one I8X6
+    plan returns the coefficients to <= 1e-6 (the FP32 inverse alone gives
+    ~2.6e-5: the forward amplifies an inverse error ~250 times at this L)."""
+    L, B = 1024, 16
+    p = plan(L, 0, "i8x6")
+    flm = inputs.coeffs(L, B, seed=5, weighted=True)
+    back = to_host(p.forward(p.inverse(to_dev(flm))))
+    assert relmax(back, flm) < 1e-6
+    del _plans[(L, 0, "i8x6")]
+
+
+def teardown_module(module):
+    _plans.clear()

@@ -43,9 +43,16 @@ def _plan(prec):
 
 
 def _release(*keys):
+    """Destroys the named cached plans now (close() frees the device memory;
+    an exception's traceback can otherwise keep a plan alive until the next
+    garbage collection)."""
+    import gc
     import torch
     for k in keys:
-        _cache.pop(k, None)
+        v = _cache.pop(k, None)
+        if hasattr(v, "close"):
+            v.close()
+    gc.collect()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
 
