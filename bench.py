@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--L", type=int, default=1024)
     ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--spin", type=int, default=0,
+                    help="spin of the workload; spin != 0 plans run their forward with OSHT_SPIN_FWD_FORCE (the "
+                         "order-by-order spin forward is unstable beyond L ~ 9: timed, its round trip reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true",
                     help="time only the listed paths (no FP64 reference path; for profiling runs)")
@@ -325,11 +328,27 @@ def run_uneven(args):
     reps.sort()
     t_graph = 0.5 * (reps[9] + reps[10])
     nmaps = sum(len(v) for v in groups.values())
+    # per-map errors of the graph's results: the inverse against an FP64
+    # plan's inverse (itself pinned to the oracle by the tests), and for
+    # spin-0 maps the round trip forward(inverse(flm)) against flm
+    per_map = []
+    for k in keys:
+        ref = Plan(k[0], k[1], precision="fp64").inverse(flm[k])
+        for j, i in enumerate(groups[k]):
+            e = {"map": i, "L": k[0], "spin": k[1],
+                 "inverse_vs_fp64": float((f[k][j] - ref[j]).abs().max() / ref[j].abs().max())}
+            if k[1] == 0:
+                e["round_trip"] = float((g[k][j] - flm[k][j]).abs().max() / flm[k][j].abs().max())
+            per_map.append(e)
+    per_map.sort(key=lambda e: e["map"])
     print(json.dumps({
         "metric": "uneven batch: 64 maps, L in {64,128,256,512}, s in {0,+-2}; inverse of all, forward of spin 0",
         "value": nmaps / (t_graph * 1e-3), "unit": "maps/s (graph replay)", "n_gpus": 1, "steps": args.steps,
         "ms_eager_job_by_job": t_eager, "ms_batch_run_streams": t_batch, "ms_graph_replay_median": t_graph,
-        "plans": len(keys), "jobs": len(jobs), "precision": "fp32-fwd", "data": "synthetic"}), flush=True)
+        "plans": len(keys), "jobs": len(jobs), "precision": "fp32-fwd", "data": "synthetic",
+        "max_inverse_vs_fp64": max(e["inverse_vs_fp64"] for e in per_map),
+        "max_round_trip_spin0": max(e["round_trip"] for e in per_map if "round_trip" in e),
+        "per_map": per_map}), flush=True)
 
 
 def run_real(args):
@@ -399,7 +418,8 @@ def main():
 
     L, B = args.L, args.batch
     torch.cuda.set_device(0)
-    flm_h = inputs.coeffs(L, B, seed=5, weighted=True)
+    spin = args.spin
+    flm_h = inputs.coeffs(L, B, seed=5, weighted=True, spin=spin)
     flm = torch.as_tensor(flm_h).cuda()
     paths = [s.strip() for s in args.paths.split(",") if s.strip()]
     if "fp64" not in paths and not args.no_fp64:
@@ -415,8 +435,8 @@ def main():
     res = {}
     for name in paths:
         # optional plan-time autotuning of the forward sweep's block shape (not timed)
-        plan = Plan(L, 0, precision=PRECISION[name], tune=args.tune,
-                    theta_cache_dir=tune_dir)
+        plan = Plan(L, spin, precision=PRECISION[name], tune=args.tune, theta_cache_dir=tune_dir,
+                    force_spin_forward=spin != 0)
         r = run_path(name, plan, flm, args.steps, args.warmup)
         r["device_bytes"] = plan.info()["device_bytes"]
         r["plan"] = plan
@@ -462,7 +482,7 @@ def main():
     from oracle import sht as osht
     from tests.gpu_util import oracle_plan
     rings = [0, 1, L // 2, L - 1]
-    ref = osht.inverse_rings(oracle_plan(L), flm_h[:2], rings)
+    ref = osht.inverse_rings(oracle_plan(L, spin), flm_h[:2], rings)
     f_h = res[head]["f"].cpu().numpy()
     inv_err = 0.0
     for k, v in ref.items():
@@ -474,7 +494,8 @@ def main():
     roof = {"bound": "mfma", "kernel": "gemm_kernel<..., RoleApplyForward> (apply_forward)",
             "achieved": hp["apply_forward"]["tflops"], "peak": peak, "unit": "TFLOP/s",
             "frac": hp["apply_forward"]["tflops"] / peak,
-            "traffic": measured_traffic(head, L, B, hp["apply_forward"]["launches"] // args.steps)}
+            "traffic": measured_traffic(head, L, B, hp["apply_forward"]["launches"] // args.steps)
+            if spin == 0 else None}
     out = {
         "metric": f"fwd+inv SHT/s at L={L}, batch {B} (mixed vs FP64, max rel err); HBM GB/s",
         "headline_rule": "fastest path whose one-step round trip (inverse then forward) is <= 1e-6, else fp64",
@@ -489,13 +510,14 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE.get(head, "f64"),
         "data": "synthetic",
-        "config": {"workload": f"spin-0 inverse then forward SHT, L={L}, batch {B}, flm N(0,1)(1+l)^-1 seed 5",
-                   "L": L, "batch": B, "spin": 0, "path": head, "parallelism": "single-gpu"},
+        "config": {"workload": f"spin-{spin} inverse then forward SHT, L={L}, batch {B}, "
+                               f"flm N(0,1)(1+l)^-1 seed 5",
+                   "L": L, "batch": B, "spin": spin, "path": head, "parallelism": "single-gpu"},
         "paths": out_paths,
         "max_rel_err_inverse_vs_oracle_sampled_rings": inv_err,
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and spin == 0:
         out["cpu_baseline"] = cpu_baseline(L)
     print(json.dumps(out), flush=True)
 
