@@ -183,6 +183,25 @@ int osht_inverse(const osht_plan_t* plan, const void* flm, void* f, int64_t batc
                  hipStream_t stream);
 
 /*
+ * Inverse SHT that allocates no device memory, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, layouts, stream semantics and
+ * results (bit for bit) as osht_inverse on the same plan, but its per-call
+ * workspace (GEMM tables, slot buffers, ring bins) is a 256 MiB static
+ * device array of the library, one copy per GPU, held until the process
+ * ends, instead of the plan's workspace.  It needs 80 * L^2 * batch bytes
+ * plus a few tables for spin 0 (about the same for spin != 0): batch up to
+ * 3 at L = 1024, 12 at L = 512, 51 at L = 256; larger requests return
+ * OSHT_EINVAL with nothing enqueued, and OSHT_PREC_I8X6 / _I8X8 plans
+ * OSHT_ENOTSUP.  Never calls hipMalloc or hipFree.
+ * All calls on one GPU share its array, which keeps the last call's
+ * contents: calls that overlap in time on one GPU (on any plans or streams)
+ * race; serialise them.
+ */
+int osht_inverse_noalloc(const osht_plan_t* plan, const void* flm, void* f, int64_t batch,
+                         hipStream_t stream);
+
+/*
  * Forward SHT (Procedure 1): coefficients from samples, removing the
  * aliases of orders |m'| > |m| in descending |m| before the order-m systems
  * P_m f_m = g_m are solved (Eq. gtof_inverse, Eq. signal_update).

@@ -172,6 +172,12 @@ class Plan:
         """Samples from coefficients (Procedure 2)."""
         return self._run("osht_inverse", flm, out)
 
+    def inverse_noalloc(self, flm, out=None):
+        """As inverse(), on the library's static scratch array instead of the
+        plan's workspace (no device allocation inside the call; pass `out`
+        to avoid torch's allocation as well)."""
+        return self._run("osht_inverse_noalloc", flm, out)
+
     def forward(self, f, out=None):
         """Coefficients from samples (Procedure 1)."""
         return self._run("osht_forward", f, out)

@@ -52,6 +52,7 @@ EXPORTED = (
     "osht_batch_run",
     "osht_graph_destroy",
     "osht_plan_status",
+    "osht_inverse_noalloc",
 )
 
 
@@ -118,7 +119,7 @@ def lib():
     L.osht_plan_info.argtypes = [vp, ctypes.POINTER(OshtInfo)]
     L.osht_plan_theta.argtypes = [vp, i32p]
     for name in ("osht_inverse", "osht_forward", "osht_inverse_adjoint", "osht_forward_adjoint", "osht_forward_real",
-                 "osht_inverse_real"):
+                 "osht_inverse_real", "osht_inverse_noalloc"):
         fn = getattr(L, name)
         fn.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
         fn.restype = ctypes.c_int

@@ -295,6 +295,11 @@ int osht_inverse(const osht_plan_t* plan, const void* flm, void* f, int64_t batc
                        [&](Plan& p, const double* a, double* b) { osht::run_inverse(p, a, b, batch, stream); });
 }
 
+int osht_inverse_noalloc(const osht_plan_t* plan, const void* flm, void* f, int64_t batch, hipStream_t stream) {
+  return run_transform(plan, flm, f, batch, stream, false,
+                       [&](Plan& p, const double* a, double* b) { osht::run_inverse_noalloc(p, a, b, batch, stream); });
+}
+
 int osht_forward(const osht_plan_t* plan, const void* f, void* flm, int64_t batch, hipStream_t stream) {
   return run_transform(plan, f, flm, batch, stream, true,
                        [&](Plan& p, const double* a, double* b) { osht::run_forward(p, a, b, batch, stream); });

@@ -292,6 +292,9 @@ void prepare_transforms(Plan& p, int64_t B);
 void invalidate_tables(Plan& p);
 // OSHT_CHECK_FINITE: scans n doubles for NaN / Inf, setting p.d_status.
 void launch_finite_scan(Plan& p, const double* x, int64_t n, hipStream_t st);
+// osht_inverse_noalloc (noalloc.hip): the inverse on the library's static
+// per-device scratch array; throws OSHT_EINVAL when L and B need more.
+void run_inverse_noalloc(Plan& p, const double* flm, double* f, int64_t B, hipStream_t st);
 // int8-digit inverse apply (ozaki.hip)
 void build_oz_planes(Plan& p);
 int oz_x_cols(const Plan& p, int64_t B);   // columns of the right-hand-side digit planes
