@@ -21,10 +21,15 @@
 // through LDS (padded by one point per 16 against bank conflicts).  Pass
 // (Ns, R) maps butterfly j, inputs x[j + r M/R], to outputs
 // y[(j / Ns) Ns R + j % Ns + r Ns] after twiddles w^r,
-// w = e^{-+2 pi i (j % Ns)/(Ns R)}, read from an e^{-2 pi i e/Mmax} table.
+// w = e^{-+2 pi i (j % Ns)/(Ns R)}: the powers w^(2^b) are read from an
+// e^{-2 pi i e/Mmax} table one pass ahead (so the loads overlap the LDS
+// exchange) and w^r is their product over the bits of r.  The inverse FFT
+// runs the forward's passes with conjugate twiddles.
 //
-// Work: one launch per FFT-size class (rings sharing M).  A workgroup runs F
-// = blockDim/T FFTs, one per (ring, map) pair of the class; pairs are
+// Work: the rings sharing M form a size class; one launch per direction
+// runs every class up to 4096 points (8192-point classes launch on their
+// own).  A workgroup runs F = blockDim/T FFTs, one per (ring, map) pair of
+// its class; pairs are
 // map-fastest so a workgroup's maps share the ring, and workgroup ids are
 // remapped so that consecutive pairs stay on one XCD (one L2) -- the map
 // -fastest bin array H[(k^2 + q) B + b] is then written by nearby pairs.
@@ -111,32 +116,54 @@ struct FftCtx {
 
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
-// One Stockham pass of radix R over the thread's 16 points, held as
-// butterflies c = 0..16/R-1 with element r of butterfly c in v[c + r (16/R)].
-template <int R, bool INV>
-__device__ __forceinline__ void pass_compute(cplx* v, const FftCtx& cx, int Ns) {
-  constexpr int NB = RPT / R;
+// The radix of pass p of an FFT of size 2^logM: 16, ..., 16, then 2, 4 or 8
+// when logM is not a multiple of 4.  Both directions run the same passes
+// (the inverse with conjugate twiddles), so pass p always follows 16^p
+// points of the transform: Ns = 16^p.
+constexpr int pass_radix(int logM, int p) { return p < (logM >> 2) ? 16 : (1 << (logM & 3)); }
+constexpr int num_passes(int logM) { return (logM + 3) >> 2; }
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
+// Base twiddles w, w^2, w^4, w^8 (log2 R of them) per butterfly of pass p > 0.
+constexpr int pass_ntw(int logM, int p) {
+  return p == 0 ? 1 : (RPT / pass_radix(logM, p)) * ilog2(pass_radix(logM, p));
+}
+
+// Loads pass P's base twiddles into pb[c log2(R) + b] = w_c^(2^b), w_c the
+// twiddle e^{-2 pi i e / (Ns R)} of butterfly c (e = its index mod Ns).
+template <int LOGM, int P>
+__device__ __forceinline__ void load_twiddles(cplx* pb, const FftCtx& cx) {
+  constexpr int R = pass_radix(LOGM, P), NB = RPT / R, LB = ilog2(R);
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
-    const int j = cx.t + c * cx.T;
-    const int e = j & (Ns - 1);
-    if (Ns > 1 && e != 0) {
-      // w^r = tw[r * E], E = e * Mmax / (Ns R); w^r from w, w^2, w^4, w^8
-      const int E = e << (cx.logMmax - (31 - __clz(Ns * R)));
-      cplx p[4];
+    const int e = (cx.t + c * cx.T) & ((1 << (4 * P)) - 1);
+    const int E = e << (cx.logMmax - 4 * P - LB);  // tw[E] = e^{-2 pi i e / (Ns R)}
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        if ((1 << b) < R) {
-          p[b] = cx.tw[E << b];
-          if (INV) p[b].y = -p[b].y;
-        }
+    for (int b = 0; b < LB; ++b) pb[c * LB + b] = cx.tw[E << b];
+  }
+}
+
+// One Stockham pass of radix R over the thread's 16 points, held as
+// butterflies c = 0..16/R-1 with element r of butterfly c in v[c + r (16/R)].
+// TW: multiply input r of each butterfly by w^r first, w^r the product of
+// the base twiddles pb[b] = w^(2^b) over the set bits b of r (ascending).
+template <int R, bool INV, bool TW>
+__device__ __forceinline__ void pass_compute(cplx* v, const cplx* pb) {
+  constexpr int NB = RPT / R, LB = ilog2(R);
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if constexpr (TW) {
+      cplx p[LB];
+#pragma unroll
+      for (int b = 0; b < LB; ++b) {
+        p[b] = pb[c * LB + b];
+        if (INV) p[b].y = -p[b].y;
       }
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         cplx w;
         bool have = false;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < LB; ++b) {
           if (r & (1 << b)) {
             w = have ? cmul(w, p[b]) : p[b];
             have = true;
@@ -173,38 +200,49 @@ __device__ __forceinline__ void pass_load(cplx* v, const FftCtx& cx) {
   }
 }
 
-// The radix of pass p (0-based) of the forward FFT: 16, ..., 16, small.
-constexpr int pass_radix(int logM, int p) { return p < (logM >> 2) ? 16 : (1 << (logM & 3)); }
-constexpr int num_passes(int logM) { return (logM + 3) >> 2; }
-constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
-
-// Pass P of an FFT of size 2^LOGM; Ns = product of the radices before it.
+// Pass P of an FFT of size 2^LOGM; pb holds its base twiddles (P > 0).
+// The next pass's twiddles are loaded right after this pass's arithmetic,
+// so they arrive while the barriers and the LDS exchange run.  `pre` runs
+// once, before the exchange that precedes the last pass (after pass 0 if
+// there is only one): loads it issues for use after the FFT overlap that
+// pass.
 template <bool INV, int LOGM, int P>
 struct FftPass {
   static constexpr int NP = num_passes(LOGM);
-  static constexpr int R = INV ? pass_radix(LOGM, NP - 1 - P) : pass_radix(LOGM, P);
-  static __device__ __forceinline__ void run(cplx* v, const FftCtx& cx, int Ns) {
+  static constexpr int R = pass_radix(LOGM, P);
+  template <class Pre>
+  static __device__ __forceinline__ void run(cplx* v, const FftCtx& cx, const cplx* pb, Pre&& pre) {
     if constexpr (P > 0) {
       __syncthreads();  // previous pass's stores visible
       pass_load<R>(v, cx);
+      pass_compute<R, INV, true>(v, pb);
+    } else {
+      pass_compute<R, INV, false>(v, nullptr);
     }
-    pass_compute<R, INV>(v, cx, Ns);
     if constexpr (P < NP - 1) {
+      cplx pn[pass_ntw(LOGM, P + 1)];
+      load_twiddles<LOGM, P + 1>(pn, cx);
+      if constexpr (P + 1 == NP - 1) pre();
       __syncthreads();  // all loads of this pass done before stores (in place)
-      pass_store<R>(v, cx, Ns);
-      FftPass<INV, LOGM, P + 1>::run(v, cx, Ns * R);
+      pass_store<R>(v, cx, 1 << (4 * P));
+      FftPass<INV, LOGM, P + 1>::run(v, cx, pn, pre);
+    } else if constexpr (NP == 1) {
+      pre();
     }
   }
 };
 
 // Full FFT of size M = 2^LOGM (LOGM >= 4), points t + i T in v on entry and
-// exit (natural order).  Every thread of the workgroup must call it (it
-// contains barriers).  Forward: radix-16 passes then the small radix;
-// inverse (unscaled): the reverse order, so that the inverse starts from
-// the forward's output ownership.
+// exit (natural order); the inverse (INV) is the same passes with conjugate
+// twiddles, unscaled.  Every thread of the workgroup must call it (it
+// contains barriers).
+template <bool INV, int LOGM, class Pre>
+__device__ __forceinline__ void fft(cplx* v, const FftCtx& cx, Pre&& pre) {
+  FftPass<INV, LOGM, 0>::run(v, cx, nullptr, pre);
+}
 template <bool INV, int LOGM>
 __device__ __forceinline__ void fft(cplx* v, const FftCtx& cx) {
-  FftPass<INV, LOGM, 0>::run(v, cx, 1);
+  fft<INV, LOGM>(v, cx, [] {});
 }
 
 // Workgroup -> pair block, keeping consecutive pair blocks on one XCD
@@ -271,16 +309,25 @@ __global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void chirp_kernel(const Rin
 
 // Shared middle of analysis and synthesis: v holds the chirped input at
 // points t + i T; on return v holds the unscaled convolution at the same
-// points.
+// points and wo the output chirp w_q (q = t + i T < n, else 0), loaded
+// during the inverse FFT's last pass.  The chirp spectrum is loaded during
+// the forward FFT's last pass.
 template <int LOGM>
-__device__ __forceinline__ void bluestein(cplx* v, const FftCtx& cx, const cplx* __restrict__ cf, bool active) {
-  fft<false, LOGM>(v, cx);
+__device__ __forceinline__ void bluestein(cplx* v, cplx* wo, const FftCtx& cx,
+                                          const cplx* __restrict__ cf, const cplx* __restrict__ w, int n,
+                                          bool active) {
+  cplx c[RPT];
+  fft<false, LOGM>(v, cx, [&] {});
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const cplx c = active ? cf[cx.t + i * cx.T] : cplx{0.0, 0.0};
-    v[i] = cmul(v[i], c);
-  }
-  fft<true, LOGM>(v, cx);
+    for (int i = 0; i < RPT; ++i) c[i] = active ? cf[cx.t + i * cx.T] : cplx{0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) v[i] = cmul(v[i], c[i]);
+  fft<true, LOGM>(v, cx, [&] {});
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int q = cx.t + i * cx.T;
+      wo[i] = (active && q < n) ? w[q] : cplx{0.0, 0.0};
+    }
 }
 
 struct RingArgs {
@@ -338,14 +385,15 @@ __device__ __forceinline__ void analysis_body(const RingArgs& a, int k0, int npa
     }
     v[i] = (pc.active && p < pc.n) ? cmul(x, w[p]) : cplx{0.0, 0.0};
   }
-  bluestein<LOGM>(v, cx, chirp_fft + pc.off, pc.active);
+  cplx wo[RPT];
+  bluestein<LOGM>(v, wo, cx, chirp_fft + pc.off, w, pc.n, pc.active);
   if (pc.active) {
     const double sc = (normalise ? 1.0 / pc.n : 1.0) / M;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int q = t + i * T;
       if (q < pc.n) {
-        const cplx c = cmul(v[i], w[q]);
+        const cplx c = cmul(v[i], wo[i]);
         H[(pc.base + q) * B + pc.b] = {c.x * sc, c.y * sc};
       }
     }
@@ -430,7 +478,8 @@ __device__ __forceinline__ void synthesis_body(const RingArgs& a, int k0, int np
     }
     v[i] = h;
   }
-  bluestein<LOGM>(v, cx, chirp_fft + pc.off, pc.active);
+  cplx wo[RPT];
+  bluestein<LOGM>(v, wo, cx, chirp_fft + pc.off, w, pc.n, pc.active);
   if (pc.active) {
     const double sc = 1.0 / M;
     cplx* fr = f + (int64_t)pc.b * L * L + pc.base;
@@ -442,7 +491,7 @@ __device__ __forceinline__ void synthesis_body(const RingArgs& a, int k0, int np
     for (int i = 0; i < RPT; ++i) {
       const int j = t + i * T;
       if (j < pc.n) {
-        const cplx c = cmul(v[i], w[j]);
+        const cplx c = cmul(v[i], wo[i]);
         if constexpr (REAL) {
           fa[j] = c.x * sc;
           if (has_b) fb[j] = -c.y * sc;
@@ -459,7 +508,7 @@ __device__ __forceinline__ void synthesis_body(const RingArgs& a, int k0, int np
 // the tail): one launch instead of one per class, whose fixed cost
 // dominated the small classes.
 template <bool SYN, bool REAL>
-__global__ __launch_bounds__(256) void ring_dft_multi_kernel(RingArgs a, ClassTab ct) {
+__global__ __launch_bounds__(256, 2) void ring_dft_multi_kernel(RingArgs a, ClassTab ct) {
   int c = 0;
   while (c + 1 < ct.n && (int)blockIdx.x >= ct.blk0[c + 1]) ++c;
   const int bid = (int)blockIdx.x - ct.blk0[c], G = ct.nblk[c];
