@@ -31,7 +31,8 @@ Prints one JSON line with, in addition:
                 `ms_per_step_graph_replay_median`, the median of 20 replays
                 of the step captured into one HIP graph);
   cpu_baseline  the FP64 CPU oracle (tests' reference implementation) timed on
-                the host on a bounded sample: one map at the metric's L (see
+                the host on a bounded sample: one map at the metric's L, its
+                per-order work timed on every 8th order and scaled (see
                 'sample').
 """
 
@@ -45,12 +46,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X dense matrix FP64 / FP32
-PRECISION = {"mixed": "fp32-fwd", "mixed-inv": "fp32", "fp64": "fp64", "i8x6": "i8x6", "i8x8": "i8x8"}
+PRECISION = {"mixed": "fp32-fwd", "mixed-inv": "fp32", "fp64": "fp64", "i8x6": "i8x6", "i8x8": "i8x8",
+             "fwd32": "fwd32"}
 DTYPE = {"mixed": "f32 applies + f64", "mixed-inv": "f32 inverse apply + f64",
+         "fwd32": "f32 forward coefficient tiles + f64",
          "i8x6": "int8 digit-split inverse apply (i32 acc) + f32/f64 forward apply + f64",
          "i8x8": "int8 digit-split inverse apply (i32 acc) + f64", "fp64": "f64"}
 # paths whose forward apply runs FP32 coefficient tiles (blended peak)
-FWD32_PATHS = ("mixed", "i8x6")
+FWD32_PATHS = ("mixed", "i8x6", "fwd32")
 # the headline must return its input to this max relative error over one
 # inverse + forward step (the mixed-precision target); a path that misses
 # it is reported beside the FP64 path, which then gives `value`
@@ -68,9 +71,12 @@ def parse():
                     help="spin of the workload; spin != 0 plans run their forward with OSHT_SPIN_FWD_FORCE (the "
                          "order-by-order spin forward is unstable beyond L ~ 9: timed, its round trip reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="time the oracle on the whole map (about 5 minutes at L=1024) instead of on a sample of "
+                         "its orders")
     ap.add_argument("--no-fp64", action="store_true",
                     help="time only the listed paths (no FP64 reference path; for profiling runs)")
-    ap.add_argument("--paths", default="i8x6,fp64,mixed,i8x8",
+    ap.add_argument("--paths", default="fwd32,i8x6,fp64,mixed,i8x8",
                     help="comma list of paths to time (fp64 is always added); the fastest one that returns its "
                          "input to 1e-6 over one step is the headline")
     ap.add_argument("--tune", action="store_true",
@@ -101,32 +107,7 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_per_launch": n * 8, "launches": 3}), flush=True)
 
 
-def cpu_baseline(L_metric):
-    """The oracle's inverse + forward of one map at the metric's band-limit
-    (B = 1; the metric's batch of 16 would take 16 times as long), timed
-    directly, not scaled: the plan (per-order tables and LU factors) is
-    built and cached first and its time is reported separately, as the GPU
-    plan is built before its timed region."""
-    import numpy as np
-
-    from oracle import sht
-    from tests import inputs
-    from tests.gpu_util import golden_theta
-
-    L = L_metric
-    t0 = time.perf_counter()
-    p = sht.Plan(L, 0, numerators=golden_theta(L), cache_bytes=float("inf"))
-    for m in range(L):
-        p._solver(m)  # tables of every order and the LU factors of every P_m, cached
-    t_plan = time.perf_counter() - t0
-    flm = inputs.coeffs(L, 1, seed=5, weighted=True)
-    t0 = time.perf_counter()
-    f = sht.inverse(p, flm)
-    t1 = time.perf_counter()
-    g = sht.forward(p, f)
-    t2 = time.perf_counter()
-    dt = t2 - t0
-    err = float(np.max(np.abs(g - flm)) / np.max(np.abs(flm)))
+def _threads():
     threads = os.cpu_count()
     try:
         from threadpoolctl import threadpool_info
@@ -135,14 +116,104 @@ def cpu_baseline(L_metric):
             threads = max(int(i.get("num_threads", 1)) for i in info)
     except Exception:
         pass
+    return threads
+
+
+def cpu_baseline(L_metric, full=False, stride=8):
+    """The oracle's inverse + forward of one map (input map 0 of the
+    workload) at the metric's band-limit L, on the host cores.
+
+    Default, a bounded sample of that map's work: the oracle's per-order
+    steps are timed for the orders |m| = 0, stride, 2 stride, .. (both
+    signs) and scaled by stride, and its per-ring steps are timed for every
+    ring.  Inverse: per order the table product A_m f_m, per ring the fold
+    and inverse DFT (the oracle's own ring loop, run on empty orders).
+    Forward: per ring the clean-ring DFT, per order the gather, the solve
+    with P_m and the alias field on the lower rings with its subtraction.
+    The sampled orders see the samples of the map, not the map with the
+    higher orders removed, which changes no operation count.  The plan's
+    tables and LU factors of the sampled orders are built first and not
+    counted, as the GPU plan is built before its timed region.
+
+    full=True times the oracle's inverse and forward of the whole map
+    directly (tables and factors of every order first: about 4 minutes of
+    plan on 8 cores before 45 s of transform)."""
+    import copy
+
+    import numpy as np
+
+    from oracle import sht
+    from tests import inputs
+    from tests.gpu_util import golden_theta
+
+    L = L_metric
+    flm = inputs.coeffs(L, 1, seed=5, weighted=True)
+    p = sht.Plan(L, 0, numerators=golden_theta(L), cache_bytes=float("inf"))
+    if full:
+        t0 = time.perf_counter()
+        for m in range(L):
+            p._solver(m)
+        t_plan = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        f = sht.inverse(p, flm)
+        t1 = time.perf_counter()
+        g = sht.forward(p, f)
+        t2 = time.perf_counter()
+        err = float(np.max(np.abs(g - flm)) / np.max(np.abs(flm)))
+        return {"value": 1.0 / (t2 - t0), "unit": "SHT/s", "cores": _threads(), "kind": "oracle",
+                "sample": f"whole map, L={L}: inverse {t1 - t0:.1f} s, forward {t2 - t1:.1f} s; plan (tables + "
+                          f"LU factors) {t_plan:.1f} s not counted; round-trip rel err {err:.1e}"}
+
+    sample = list(range(0, L, stride))
+    t0 = time.perf_counter()
+    for am in sample:
+        p._solver(am)
+    t_plan = time.perf_counter() - t0
+    signed = [m for am in sample for m in ((am, -am) if am else (0,))]
+    x = flm[0][None, :]
+
+    # inverse: orders
+    t0 = time.perf_counter()
+    for m in signed:
+        ell = np.arange(p.l0(m), L)
+        _ = p.table(m) @ x[:, ell * ell + ell + m].T
+    t_inv_orders = time.perf_counter() - t0
+    # inverse: the oracle's ring loop (a view of the plan listing no orders)
+    empty = copy.copy(p)
+    empty.orders = lambda: range(0)
+    t0 = time.perf_counter()
+    f = sht.inverse(empty, flm)
+    t_inv_rings = time.perf_counter() - t0
+
+    # forward: clean-ring DFT of every ring
+    f = np.asarray(f)
+    work = f.copy()
+    geometry = sht.ring_geometry(L)
+    t0 = time.perf_counter()
+    spectra = {k: sht._clean_ring_spectrum(work, k) for k in range(L)}
+    t_fwd_rings = time.perf_counter() - t0
+    # forward: orders
+    t0 = time.perf_counter()
+    for am in sample:
+        for m in ((am, -am) if am else (0,)):
+            g = np.stack([spectra[k][:, m % (2 * k + 1)] for k in range(am, L)], axis=1)
+            fm = p.solve(m, g)
+            if am > 0:
+                work[:, :am * am] -= sht._order_field_on_lower_rings(p, m, fm, geometry)
+    t_fwd_orders = time.perf_counter() - t0
+
+    t_inv = t_inv_rings + stride * t_inv_orders
+    t_fwd = t_fwd_rings + stride * t_fwd_orders
     return {
-        "value": 1.0 / dt,
+        "value": 1.0 / (t_inv + t_fwd),
         "unit": "SHT/s",
-        "cores": threads,
+        "cores": _threads(),
         "kind": "oracle",
-        "sample": f"oracle inverse+forward of one map at L={L} (input map 0 of the workload): inverse {t1 - t0:.1f} s, "
-                  f"forward {t2 - t1:.1f} s; plan (tables + LU factors, cached) {t_plan:.1f} s not counted; "
-                  f"round-trip rel err {err:.1e}",
+        "sample": f"one map at L={L}: the oracle's per-order steps on |m| = 0, {stride}, .., {sample[-1]} "
+                  f"({len(signed)} of {2 * L - 1} orders) scaled by {stride}, its per-ring steps on all {L} rings; "
+                  f"inverse {t_inv:.1f} s (rings {t_inv_rings:.1f} + {stride} x {t_inv_orders:.2f}), forward "
+                  f"{t_fwd:.1f} s (rings {t_fwd_rings:.1f} + {stride} x {t_fwd_orders:.2f}); the sampled orders' "
+                  f"plan (tables + LU factors) {t_plan:.1f} s not counted",
     }
 
 
@@ -438,6 +509,7 @@ def main():
         plan = Plan(L, spin, precision=PRECISION[name], tune=args.tune, theta_cache_dir=tune_dir,
                     force_spin_forward=spin != 0)
         r = run_path(name, plan, flm, args.steps, args.warmup)
+        print(f"bench: path {name} timed, {B * args.steps / r['seconds']:.1f} SHT/s", file=sys.stderr, flush=True)
         r["device_bytes"] = plan.info()["device_bytes"]
         r["plan"] = plan
         res[name] = r
@@ -518,7 +590,8 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu_baseline and spin == 0:
-        out["cpu_baseline"] = cpu_baseline(L)
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(L, full=args.cpu_baseline_full)
     print(json.dumps(out), flush=True)
 
 

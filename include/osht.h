@@ -69,6 +69,9 @@ extern "C" {
                                         adjoint reads FP64 A_m. */
 #define OSHT_PREC_I8X8        0x4u   /* as OSHT_PREC_I8X6 with 8 digits (~1e-14, FP64 grade) and the
                                         forward in FP64 */
+#define OSHT_PREC_FWD32       0x5u   /* the inverse (and both adjoints) in FP64; the forward's
+                                        coefficient rows P_m^{-1} on FP32 matrix cores as in
+                                        OSHT_PREC_FP32_FWD, its alias rows in FP64 */
 #define OSHT_PREC_MASK        0x0fu
 /* colatitude placement (Sec. III-D) */
 #define OSHT_THETA_GREEDY       0x00u  /* condition-number-minimising greedy */

@@ -55,7 +55,8 @@ class Plan:
         and buffers FP64), "fp32-fwd" (also the forward's P_m^{-1} rows in
         FP32; its alias rows stay FP64), "i8x6" (the inverse apply as exact
         int8 matrix-core products of 6-digit splits, ~2e-10; the forward as
-        "fp32-fwd") or "i8x8" (8 digits, FP64 grade; the forward FP64).
+        "fp32-fwd"), "i8x8" (8 digits, FP64 grade; the forward FP64) or
+        "fwd32" (the inverse FP64, the forward as "fp32-fwd").
         tune: time the forward sweep's block shapes on this device and keep
         the fastest (cached in theta_cache_dir).
         force_spin_forward: run the forward of a spin != 0 plan even when the
@@ -68,9 +69,9 @@ class Plan:
         if placement not in ("greedy", "alternating"):
             raise ValueError("placement must be 'greedy' or 'alternating'")
         prec = {"fp64": _lib.OSHT_PREC_FP64, "fp32": _lib.OSHT_PREC_FP32, "fp32-fwd": _lib.OSHT_PREC_FP32_FWD,
-                "i8x6": _lib.OSHT_PREC_I8X6, "i8x8": _lib.OSHT_PREC_I8X8}
+                "i8x6": _lib.OSHT_PREC_I8X6, "i8x8": _lib.OSHT_PREC_I8X8, "fwd32": _lib.OSHT_PREC_FWD32}
         if precision not in prec:
-            raise ValueError("precision must be 'fp64', 'fp32', 'fp32-fwd', 'i8x6' or 'i8x8'")
+            raise ValueError("precision must be 'fp64', 'fp32', 'fp32-fwd', 'i8x6', 'i8x8' or 'fwd32'")
         flags = prec[precision] | (
             _lib.OSHT_THETA_GREEDY if placement == "greedy" else _lib.OSHT_THETA_ALTERNATING) | (
             _lib.OSHT_TUNE if tune else 0) | (

@@ -25,6 +25,7 @@ OSHT_PREC_FP32 = 0x1
 OSHT_PREC_FP32_FWD = 0x2
 OSHT_PREC_I8X6 = 0x3
 OSHT_PREC_I8X8 = 0x4
+OSHT_PREC_FWD32 = 0x5
 OSHT_THETA_GREEDY = 0x00
 OSHT_THETA_ALTERNATING = 0x10
 OSHT_TUNE = 0x100

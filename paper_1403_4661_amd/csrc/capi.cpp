@@ -211,8 +211,8 @@ int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_di
   if (spin <= -L || spin >= L) return fail(OSHT_EINVAL, "|spin| must be < L");
   const uint32_t prec = flags & OSHT_PREC_MASK, theta = flags & OSHT_THETA_MASK;
   if (prec != OSHT_PREC_FP64 && prec != OSHT_PREC_FP32 && prec != OSHT_PREC_FP32_FWD && prec != OSHT_PREC_I8X6 &&
-      prec != OSHT_PREC_I8X8)
-    return fail(OSHT_ENOTSUP, "precision must be OSHT_PREC_FP64, _FP32, _FP32_FWD, _I8X6 or _I8X8");
+      prec != OSHT_PREC_I8X8 && prec != OSHT_PREC_FWD32)
+    return fail(OSHT_ENOTSUP, "precision must be OSHT_PREC_FP64, _FP32, _FP32_FWD, _I8X6, _I8X8 or _FWD32");
   if (theta != OSHT_THETA_GREEDY && theta != OSHT_THETA_ALTERNATING) return fail(OSHT_EINVAL, "unknown placement flag");
   if (flags & ~(OSHT_PREC_MASK | OSHT_THETA_MASK | OSHT_TUNE | OSHT_SPIN_FWD_FORCE | OSHT_CHECK_FINITE))
     return fail(OSHT_EINVAL, "unknown flag bits");
@@ -224,7 +224,7 @@ int osht_plan_create(int L, int spin, uint32_t flags, const char* theta_cache_di
     p.spin = spin;
     p.flags = flags;
     p.fp32 = prec == OSHT_PREC_FP32 || prec == OSHT_PREC_FP32_FWD;
-    p.fp32_fwd = prec == OSHT_PREC_FP32_FWD || prec == OSHT_PREC_I8X6;
+    p.fp32_fwd = prec == OSHT_PREC_FP32_FWD || prec == OSHT_PREC_I8X6 || prec == OSHT_PREC_FWD32;
     p.oz = prec == OSHT_PREC_I8X6 ? 6 : prec == OSHT_PREC_I8X8 ? 8 : 0;
     if (theta_cache_dir) p.cache_dir = theta_cache_dir;
     OSHT_HIP(hipGetDevice(&p.device));

@@ -222,9 +222,9 @@ struct Plan {
   DevBuf d_cos, d_sin, d_cosh, d_sinh;
   DevBuf d_slots;
   DevBuf d_A, d_Q;            // FP64 blocks (FP32 plans release d_A and keep d_Q for the alias rows)
-  DevBuf d_A32, d_Q32;        // FP32 copies, same element offsets (d_Q32 for OSHT_PREC_FP32_FWD only)
+  DevBuf d_A32, d_Q32;        // FP32 copies, same element offsets (d_Q32 when fp32_fwd)
   bool fp32 = false;          // inverse-side applies on FP32 A_m (OSHT_PREC_FP32, OSHT_PREC_FP32_FWD)
-  bool fp32_fwd = false;      // forward coefficient rows on FP32 P_m^{-1} (OSHT_PREC_FP32_FWD, OSHT_PREC_I8X6)
+  bool fp32_fwd = false;      // forward coefficient rows on FP32 P_m^{-1} (OSHT_PREC_FP32_FWD, _I8X6, _FWD32)
   // inverse apply on int8 digit splits of A_m and X_m (OSHT_PREC_I8X6 / _I8X8):
   // the number of digits, 0 when off; d_A (FP64) stays for the adjoint
   int oz = 0;

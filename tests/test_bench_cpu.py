@@ -70,3 +70,18 @@ def test_more_than_one_gpu_is_refused():
                        timeout=120)
     assert r.returncode == 2
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_cpu_baseline_sample_and_full():
+    """The order-sampled oracle timing and the whole-map one both run and
+    report what they timed; at stride 1 the sample covers every order, so
+    the two time the same work (wide bound: they are separate timings)."""
+    import bench
+    full = bench.cpu_baseline(96, full=True)
+    samp = bench.cpu_baseline(96, stride=1)
+    assert full["kind"] == samp["kind"] == "oracle" and full["unit"] == samp["unit"] == "SHT/s"
+    assert "round-trip rel err" in full["sample"] and "191 of 191 orders" in samp["sample"]
+    assert float(full["sample"].split("round-trip rel err ")[1]) < 1e-10
+    assert 0.2 < samp["value"] / full["value"] < 5.0
+    s8 = bench.cpu_baseline(96)
+    assert "(23 of 191 orders) scaled by 8" in s8["sample"]

@@ -50,7 +50,7 @@ def test_plan_create_rejects_bad_arguments(L, spin, flags):
 def test_plan_create_rejects_unsupported_precision():
     lib = _lib()
     h = ctypes.c_void_p()
-    assert lib.osht_plan_create(8, 0, 0x5, None, ctypes.byref(h)) == -5
+    assert lib.osht_plan_create(8, 0, 0x6, None, ctypes.byref(h)) == -5
 
 
 def test_transforms_reject_null_plan_and_pointers():

@@ -32,10 +32,11 @@ pytestmark = pytest.mark.gpu
 L, B, SEED = 1024, 16, 5
 RINGS = [0, 1, 511, 512, 1023]
 MAPS = [0, 15]
-PRECISIONS = ["fp64", "fp32", "fp32-fwd", "i8x6", "i8x8"]
-TOL = {"fp64": 1e-11, "fp32": 1e-6, "fp32-fwd": 1e-6, "i8x6": 1e-6, "i8x8": 1e-11}
-# the inverse alone: the int8 digit splits are finer than FP32
-TOL_INV = dict(TOL, i8x6=1e-8)
+PRECISIONS = ["fp64", "fp32", "fp32-fwd", "i8x6", "i8x8", "fwd32"]
+TOL = {"fp64": 1e-11, "fp32": 1e-6, "fp32-fwd": 1e-6, "i8x6": 1e-6, "i8x8": 1e-11, "fwd32": 1e-6}
+# the inverse alone: the int8 digit splits are finer than FP32; fwd32 runs
+# the FP64 inverse
+TOL_INV = dict(TOL, i8x6=1e-8, fwd32=1e-11)
 
 _cache = {}
 
@@ -120,3 +121,12 @@ def test_headline_repeat_calls_bitwise():
     f = fp64_samples()
     a, b = to_host(p.forward(f)), to_host(p.forward(f))
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fwd32", "i8x6"])
+def test_headline_round_trip_gate(precision):
+    """Inverse then forward on one plan returns the headline input to
+    <= 1e-6 (the gate bench.py applies to its headline path): the forward's
+    FP32 coefficient rows alone stay well inside it."""
+    back = to_host(plan(precision).forward(plan(precision).inverse(to_dev(flm_host()))))
+    assert relmax(back, flm_host()) < 1e-6
