@@ -225,6 +225,7 @@ struct Plan {
   DevBuf d_A32, d_Q32;        // FP32 copies, same element offsets (d_Q32 when fp32_fwd)
   bool fp32 = false;          // inverse-side applies on FP32 A_m (OSHT_PREC_FP32, OSHT_PREC_FP32_FWD)
   bool fp32_fwd = false;      // forward coefficient rows on FP32 P_m^{-1} (OSHT_PREC_FP32_FWD, _I8X6, _FWD32)
+  int gvar_fwd = 0, gvar_inv = 0;  // stream shapes of the forward and inverse applies (launch_gemm var)
   // inverse apply on int8 digit splits of A_m and X_m (OSHT_PREC_I8X6 / _I8X8):
   // the number of digits, 0 when off; d_A (FP64) stays for the adjoint
   int oz = 0;
@@ -318,8 +319,11 @@ void batch_run(const osht_job_t* jobs, int n, hipStream_t stream, osht_graph_t**
 // ApplyInverse32: FP32 A and FP32 B (the inverse apply of FP32 plans).
 enum class GemmRole { Plan, ApplyInverse, ApplyInverse32, ApplyForward, Correction, Adjoint };
 // With e0/e1, the events take the launch's start and end timestamps.
+// var: stream shape of the applies (0 default; 1, 2 alternatives the tuner
+// times; all give the same bits).
 void launch_gemm(GemmRole role, const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st,
-                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, int var = 0);
+constexpr int kGemmVars = 3;
 // Builds tasks for descriptors (64 x 64 tiles).
 void gemm_tasks(const std::vector<GemmDesc>& descs, std::vector<GemmTask>& tasks);
 
@@ -334,10 +338,11 @@ void launch_ring_analysis(const Plan& p, const double* f, double* H, int64_t B, 
 void build_fwd_blocks(Plan& p, int b);
 // builds the blocks for b; true when the delta solve's LDS need fits
 bool fwd_blocks_fit(Plan& p, int b);
-// times the forward for candidate (b, delta-solve columns per group) and
-// keeps the fastest; results cached per (device, L, spin, precision) in
-// Plan::cache_dir when set
-void tune_forward_blocks(Plan& p);
+// OSHT_TUNE: times the forward for every candidate (b, delta-solve columns
+// per group, stream shape of its apply) and the inverse for every stream
+// shape of its apply, and keeps the fastest; results cached per (device, L,
+// spin, precision) in Plan::cache_dir when set
+void autotune(Plan& p);
 void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipStream_t st, int64_t real_maps = 0);
 void run_forward_adjoint_blocked(Plan& p, const double* flmbar, double* fbar, int64_t B, hipStream_t st);
 

@@ -412,7 +412,7 @@ __device__ __forceinline__ void gemm_tile_stream(const GemmDesc& d, const GemmTa
 constexpr int kSmemDoubles = 2 * 2 * TK * (TM + Pad<double>::v);
 static_assert(2 * TK * (TM + Pad<float>::v) * 2 * sizeof(float) <= kSmemDoubles * sizeof(double), "LDS size");
 
-// Stream shape per role (k depth, stages), measured on MI355X.  FP64 tiles
+// Default stream shape (k depth, stages), measured on MI355X.  FP64 tiles
 // run 16 deep in 2 stages (32 KB of LDS): in the forward's per-block
 // launches so that four workgroups fit a CU (three 48 KB stages allowed three
 // and the step was 0.03-0.09 ms slower), in the FP64 inverse apply 1.41 ->
@@ -421,24 +421,26 @@ static_assert(2 * TK * (TM + Pad<float>::v) * 2 * sizeof(float) <= kSmemDoubles 
 // slightly slower), so the forward blocks take 32 KB.  The FP32 inverse apply runs
 // 16-deep tiles in 2 stages (16 KB): 0.76 -> 0.74 ms against 32-deep ones;
 // 3 stages of 32 or of 16 were slower.
-template <class Role> struct StreamCfg {
-  static constexpr int TK = 16, NS = 2, NS32 = 2;
-  static constexpr bool W22 = true;
-};
-template <> struct StreamCfg<RoleApplyInverse> {
-  static constexpr int TK = 16, NS = 2, NS32 = 2;
-  static constexpr bool W22 = true;
-};
-template <> struct StreamCfg<RoleApplyInverse32> {
-  static constexpr int TK = 16, NS = 2, NS32 = 2;
+//
+// Stream shapes of the streaming roles (k depth TK, stages NS for FP64 A
+// and NS32 for FP32 A), V = 0 the default and 1, 2 the alternatives that the
+// plan-time tuner (OSHT_TUNE) also times for the inverse and forward
+// applies.  Every shape sums k in the same order (FP64: one MFMA k-step of
+// 4 after another; FP32 A: partial sums over 16 k added into FP64), so the
+// shapes give bit-identical results.
+template <int V> struct StreamVar;
+template <> struct StreamVar<0> { static constexpr int TK = 16, NS = 2, NS32 = 2; };
+template <> struct StreamVar<1> { static constexpr int TK = 16, NS = 3, NS32 = 3; };
+template <> struct StreamVar<2> { static constexpr int TK = 32, NS = 2, NS32 = 2; };
+template <class Role, int V> struct StreamCfg : StreamVar<V> {
   static constexpr bool W22 = true;
 };
 
 // Each task's descriptor selects the matrix precision (GemmDesc::fp32).
-template <bool ARF, bool BCF, class Role>
+template <bool ARF, bool BCF, class Role, int V>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs,
                                                    const GemmTask* __restrict__ tasks) {
-  typedef StreamCfg<Role> SC;
+  typedef StreamCfg<Role, V> SC;
   constexpr bool kF32 = std::is_same<Role, RoleApplyInverse32>::value;
   constexpr int kStream64 = SC::NS * StreamShape<double, SC::TK>::STAGE / 8;
   constexpr int kStream32 = SC::NS32 * StreamShape<float, SC::TK, double>::STAGE / 8;
@@ -479,15 +481,25 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
 
 // With events, they take the dispatch's own start and end timestamps
 // (hipExtLaunchKernel), so timing adds no packets between launches.
-template <bool ARF, bool BCF, class Role>
+template <bool ARF, bool BCF, class Role, int V>
 void launch(const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st, hipEvent_t e0,
             hipEvent_t e1) {
   if (e0) {
     void* args[] = {(void*)&d_desc, (void*)&d_task};
-    OSHT_HIP(hipExtLaunchKernel((const void*)gemm_kernel<ARF, BCF, Role>, dim3(ntask), dim3(256), args, 0, st, e0, e1,
-                                0));
+    OSHT_HIP(hipExtLaunchKernel((const void*)gemm_kernel<ARF, BCF, Role, V>, dim3(ntask), dim3(256), args, 0, st, e0,
+                                e1, 0));
   } else {
-    hipLaunchKernelGGL((gemm_kernel<ARF, BCF, Role>), dim3(ntask), dim3(256), 0, st, d_desc, d_task);
+    hipLaunchKernelGGL((gemm_kernel<ARF, BCF, Role, V>), dim3(ntask), dim3(256), 0, st, d_desc, d_task);
+  }
+}
+
+template <class Role>
+void launch_var(int var, const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st, hipEvent_t e0,
+                hipEvent_t e1) {
+  switch (var) {
+    case 1: launch<true, true, Role, 1>(d_desc, d_task, ntask, st, e0, e1); break;
+    case 2: launch<true, true, Role, 2>(d_desc, d_task, ntask, st, e0, e1); break;
+    default: launch<true, true, Role, 0>(d_desc, d_task, ntask, st, e0, e1); break;
   }
 }
 
@@ -503,15 +515,15 @@ void gemm_tasks(const std::vector<GemmDesc>& descs, std::vector<GemmTask>& tasks
 }
 
 void launch_gemm(GemmRole role, const GemmDesc* d_desc, const GemmTask* d_task, int ntask, hipStream_t st,
-                 hipEvent_t e0, hipEvent_t e1) {
+                 hipEvent_t e0, hipEvent_t e1, int var) {
   if (ntask <= 0) return;
   switch (role) {
-    case GemmRole::Plan: launch<true, false, RolePlan>(d_desc, d_task, ntask, st, e0, e1); break;
-    case GemmRole::ApplyInverse: launch<true, true, RoleApplyInverse>(d_desc, d_task, ntask, st, e0, e1); break;
-    case GemmRole::ApplyInverse32: launch<true, true, RoleApplyInverse32>(d_desc, d_task, ntask, st, e0, e1); break;
-    case GemmRole::ApplyForward: launch<true, true, RoleApplyForward>(d_desc, d_task, ntask, st, e0, e1); break;
-    case GemmRole::Correction: launch<true, true, RoleCorrection>(d_desc, d_task, ntask, st, e0, e1); break;
-    case GemmRole::Adjoint: launch<false, true, RoleAdjoint>(d_desc, d_task, ntask, st, e0, e1); break;
+    case GemmRole::Plan: launch<true, false, RolePlan, 0>(d_desc, d_task, ntask, st, e0, e1); break;
+    case GemmRole::ApplyInverse: launch_var<RoleApplyInverse>(var, d_desc, d_task, ntask, st, e0, e1); break;
+    case GemmRole::ApplyInverse32: launch_var<RoleApplyInverse32>(var, d_desc, d_task, ntask, st, e0, e1); break;
+    case GemmRole::ApplyForward: launch_var<RoleApplyForward>(var, d_desc, d_task, ntask, st, e0, e1); break;
+    case GemmRole::Correction: launch<true, true, RoleCorrection, 0>(d_desc, d_task, ntask, st, e0, e1); break;
+    case GemmRole::Adjoint: launch<false, true, RoleAdjoint, 0>(d_desc, d_task, ntask, st, e0, e1); break;
   }
   OSHT_HIP(hipGetLastError());
 }

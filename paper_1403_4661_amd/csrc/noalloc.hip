@@ -148,7 +148,7 @@ void run_inverse_noalloc(Plan& p, const double* flm, double* f, int64_t B, hipSt
   launch_coef_to_slots(p, flm, X, B, st, p.fp32, 0);
   launch_gemm(p.fp32 ? GemmRole::ApplyInverse32 : GemmRole::ApplyInverse,
               reinterpret_cast<const GemmDesc*>(base + l.desc), reinterpret_cast<const GemmTask*>(base + l.task),
-              l.ntask, st);
+              l.ntask, st, nullptr, nullptr, p.gvar_inv);
   launch_fold(p, Y, H, B, st);
   launch_ring_synthesis(p, H, 0, f, B, st, 0);
 }

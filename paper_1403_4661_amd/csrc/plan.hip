@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <string>
 
@@ -531,7 +532,15 @@ void build_plan(Plan& p) {
   };
   if (p.fp32) narrow(p.d_A, p.d_A32, true);
   if (p.fp32_fwd) narrow(p.d_Q, p.d_Q32, false);
-  if ((p.flags & OSHT_TUNE) && !env) tune_forward_blocks(p);
+  if ((p.flags & OSHT_TUNE) && !env) autotune(p);
+  // forced stream shapes of the forward and inverse applies, "fwd,inv" (tests)
+  if (const char* ev = std::getenv("OSHT_GEMM_VAR")) {
+    int f = 0, i = 0;
+    if (std::sscanf(ev, "%d,%d", &f, &i) == 2 && f >= 0 && f < kGemmVars && i >= 0 && i < kGemmVars) {
+      p.gvar_fwd = f;
+      p.gvar_inv = i;
+    }
+  }
   OSHT_HIP(hipDeviceSynchronize());
 }
 

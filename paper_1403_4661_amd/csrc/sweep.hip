@@ -806,21 +806,24 @@ std::string tune_path(const Plan& p) {
   for (char& c : arch)
     if (c == ':' || c == '/' || c == ' ') c = '_';
   return p.cache_dir + "/tune_fwd_" + arch + "_L" + std::to_string(p.L) + "_s" + std::to_string(p.spin) + "_p" +
-         std::to_string(p.fp32_fwd ? 2 : p.fp32 ? 1 : 0) + ".txt";
+         std::to_string((p.fp32 ? 1 : 0) + (p.fp32_fwd ? 2 : 0) + 4 * p.oz) + ".txt";
 }
 
 }  // namespace
 
-void tune_forward_blocks(Plan& p) {
+void autotune(Plan& p) {
   const std::string path = tune_path(p);
-  int best_b = -1, best_c = -1;
+  int best_b = -1, best_c = -1, best_fv = 0, best_iv = 0;
   if (!path.empty()) {
     if (FILE* fp = std::fopen(path.c_str(), "r")) {
-      if (std::fscanf(fp, "%d %d", &best_b, &best_c) != 2) best_b = best_c = -1;
+      if (std::fscanf(fp, "%d %d %d %d", &best_b, &best_c, &best_fv, &best_iv) != 4 || best_fv < 0 ||
+          best_fv >= kGemmVars || best_iv < 0 || best_iv >= kGemmVars)
+        best_b = best_c = -1;
       std::fclose(fp);
     }
   }
   if (best_b < 1 || best_c < 1) {
+    best_fv = best_iv = 0;
     const int64_t Bt = p.spin == 0 ? 16 : 8;
     const int64_t n = 2 * (int64_t)p.L * p.L * Bt;
     DevBuf in, out;
@@ -831,23 +834,39 @@ void tune_forward_blocks(Plan& p) {
     hipEvent_t e0, e1;
     OSHT_HIP(hipEventCreate(&e0));
     OSHT_HIP(hipEventCreate(&e1));
-    float best_ms = 1e30f;
     const bool prof = p.prof.enabled;
     p.prof.enabled = false;
-    for (int cpw : {1, 2, 4}) {
-      for (int b : {8, 12, 16, 24, 32, 48, 64}) {
-        if (b > p.L) continue;
-        p.fb.cpw = cpw;
-        if (!fwd_blocks_fit(p, b) && b > 1) continue;
-        invalidate_tables(p);
-        run_forward(p, in.as<double>(), out.as<double>(), Bt, 0);
-        OSHT_HIP(hipEventRecord(e0, 0));
-        for (int r = 0; r < 3; ++r) run_forward(p, in.as<double>(), out.as<double>(), Bt, 0);
-        OSHT_HIP(hipEventRecord(e1, 0));
-        OSHT_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        OSHT_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) { best_ms = ms; best_b = b; best_c = cpw; }
+    // three calls after a warm one, between events on the null stream
+    auto time3 = [&](auto&& call) {
+      call();
+      OSHT_HIP(hipEventRecord(e0, 0));
+      for (int r = 0; r < 3; ++r) call();
+      OSHT_HIP(hipEventRecord(e1, 0));
+      OSHT_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      OSHT_HIP(hipEventElapsedTime(&ms, e0, e1));
+      return ms;
+    };
+    float best_ms = 1e30f;
+    for (int fv = 0; fv < kGemmVars; ++fv) {
+      p.gvar_fwd = fv;
+      for (int cpw : {1, 2, 4}) {
+        for (int b : {8, 12, 16, 24, 32, 48, 64}) {
+          if (b > p.L) continue;
+          p.fb.cpw = cpw;
+          if (!fwd_blocks_fit(p, b) && b > 1) continue;
+          invalidate_tables(p);
+          const float ms = time3([&] { run_forward(p, in.as<double>(), out.as<double>(), Bt, 0); });
+          if (ms < best_ms) { best_ms = ms; best_b = b; best_c = cpw; best_fv = fv; }
+        }
+      }
+    }
+    float best_inv = 1e30f;
+    if (p.oz == 0) {  // the int8 inverse apply has a shape of its own
+      for (int iv = 0; iv < kGemmVars; ++iv) {
+        p.gvar_inv = iv;
+        const float ms = time3([&] { run_inverse(p, out.as<double>(), in.as<double>(), Bt, 0); });
+        if (ms < best_inv) { best_inv = ms; best_iv = iv; }
       }
     }
     p.prof.enabled = prof;
@@ -857,13 +876,17 @@ void tune_forward_blocks(Plan& p) {
     if (!path.empty() && best_b > 0) {
       const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
       if (FILE* fp = std::fopen(tmp.c_str(), "w")) {
-        std::fprintf(fp, "%d %d\n# forward block levels, delta-solve columns per workgroup (%.3f ms for 3 forwards)\n",
-                     best_b, best_c, best_ms);
+        std::fprintf(fp,
+                     "%d %d %d %d\n# forward block levels, delta-solve columns per workgroup, forward-apply and "
+                     "inverse-apply stream shapes (%.3f ms for 3 forwards, %.3f ms for 3 inverses)\n",
+                     best_b, best_c, best_fv, best_iv, best_ms, p.oz == 0 ? best_inv : 0.f);
         if (std::fclose(fp) == 0) std::rename(tmp.c_str(), path.c_str());
         else std::remove(tmp.c_str());
       }
     }
   }
+  p.gvar_fwd = best_fv;
+  p.gvar_inv = best_iv;
   if (best_b < 1) return;
   p.fb.cpw = best_c;
   if (!fwd_blocks_fit(p, best_b)) {

@@ -505,13 +505,16 @@ void launch_coef_to_slots(const Plan& p, const double* flm, double* X, int64_t B
 void gemm_tasks_launch(Plan& p, const GemmTask* d_tasks, int count, GemmRole role, const char* prof_name,
                        hipStream_t st) {
   if (count <= 0) return;
+  const int var = role == GemmRole::ApplyForward                                       ? p.gvar_fwd
+                  : (role == GemmRole::ApplyInverse || role == GemmRole::ApplyInverse32) ? p.gvar_inv
+                                                                                         : 0;
   if (p.prof.wants(prof_name)) {
     hipEvent_t e0 = p.prof.get(), e1 = p.prof.get();
-    launch_gemm(role, p.tab->d_gdesc.as<GemmDesc>(), d_tasks, count, st, e0, e1);
+    launch_gemm(role, p.tab->d_gdesc.as<GemmDesc>(), d_tasks, count, st, e0, e1, var);
     p.prof.stat(prof_name).pending.emplace_back(e0, e1);
     return;
   }
-  launch_gemm(role, p.tab->d_gdesc.as<GemmDesc>(), d_tasks, count, st);
+  launch_gemm(role, p.tab->d_gdesc.as<GemmDesc>(), d_tasks, count, st, nullptr, nullptr, var);
 }
 
 namespace {

@@ -210,8 +210,10 @@ def test_forward_delta_paths(L, s, b, B, dense, monkeypatch):
 
 
 def test_autotuned_plan_matches_oracle_and_caches_choice(tmp_path):
-    """OSHT_TUNE: the forward block shape is timed on the device and cached;
-    a second plan reads the cached choice; results stay at oracle parity."""
+    """OSHT_TUNE: the forward block shape and the applies' stream shapes are
+    timed on the device and cached; a second plan reads the cached choice;
+    results stay at oracle parity, and every stream shape gives the same
+    bits as the default one."""
     import shutil
     from oracle import sht
     from paper_1403_4661_amd import THETA_CACHE_DIR, Plan
@@ -220,11 +222,34 @@ def test_autotuned_plan_matches_oracle_and_caches_choice(tmp_path):
     p = Plan(L, 0, theta_cache_dir=str(tmp_path), tune=True)
     files = [f for f in tmp_path.iterdir() if f.name.startswith("tune_fwd_")]
     assert len(files) == 1
-    b, cpw = (int(x) for x in files[0].read_text().split()[:2])
-    assert 1 <= b <= L and cpw in (1, 2, 4)
+    b, cpw, fv, iv = (int(x) for x in files[0].read_text().split()[:4])
+    assert 1 <= b <= L and cpw in (1, 2, 4) and fv in (0, 1, 2) and iv in (0, 1, 2)
     p2 = Plan(L, 0, theta_cache_dir=str(tmp_path), tune=True)
     flm = inputs.coeffs(L, 3, seed=21)
     f = sht.inverse(oplan(L), flm)
     ref = sht.forward(oplan(L), f)
     for q in (p, p2):
         assert relmax(to_host(q.forward(to_dev(f))), ref) < 1e-11
+    # the stream shapes sum k in the same order: the inverse is bit-identical
+    # to an untuned plan's (the forward may differ in rounding if b differs)
+    p0 = Plan(L, 0, theta_cache_dir=str(tmp_path))
+    x = to_dev(flm)
+    assert bool((p.inverse(x) == p0.inverse(x)).all())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fwd32", "fp32"])
+@pytest.mark.parametrize("var", ["1,1", "2,2"])
+def test_apply_stream_shapes_bit_identical(monkeypatch, precision, var):
+    """The alternative stream shapes of the applies (k depth 16 in 3 stages,
+    k depth 32 in 2) sum k in the default shape's order, so a plan forced to
+    them gives the same bits in both directions (L = 100: ragged row, column
+    and k tiles; batch 5)."""
+    from paper_1403_4661_amd import Plan
+    L, B = 100, 5
+    flm = to_dev(inputs.coeffs(L, B, seed=41, weighted=True))
+    p0 = Plan(L, 0, precision=precision)
+    monkeypatch.setenv("OSHT_GEMM_VAR", var)
+    p1 = Plan(L, 0, precision=precision)
+    f0, f1 = p0.inverse(flm), p1.inverse(flm)
+    assert bool((f0 == f1).all())
+    assert bool((p0.forward(f0) == p1.forward(f0)).all())
