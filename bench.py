@@ -314,9 +314,10 @@ def run_path(name, plan, flm, steps, warmup):
     n, ms = plan.kernel_time("apply_forward")
     breakdown = {}
     for kname in ("apply_inverse", "apply_forward", "apply_forward_correction", "delta_solve", "gather_forward",
-                  "ring_analysis", "ring_synthesis", "fold"):
+                  "ring_analysis", "ring_synthesis", "fold", "coef_to_slots", "slots_to_coef", "split_digits"):
         kn, kms = plan.kernel_time(kname)
-        breakdown[kname] = {"launches_per_step": kn / steps, "ms_per_step": kms / steps}
+        if kn > 0:
+            breakdown[kname] = {"launches_per_step": kn / steps, "ms_per_step": kms / steps}
     plan.set_profiling(False)
     # the same step captured once into a HIP graph (osht_batch_run) and
     # replayed: median of 20 replays, each timed by events on the stream

@@ -300,8 +300,10 @@ int osht_graph_destroy(osht_graph_t* graph);
  * their summed duration in milliseconds since profiling was (re)enabled.
  * Names: "apply_inverse", "apply_forward", "apply_forward_correction",
  * "apply_inverse_adjoint", "apply_forward_adjoint" (order-wise GEMMs),
- * "ring_analysis", "ring_synthesis" (ring DFTs, one launch per FFT size
- * class), "fold", "gather_forward", "delta_solve".
+ * "ring_analysis", "ring_synthesis" (ring DFTs, one launch per direction up
+ * to 4096 points), "fold", "gather_forward", "delta_solve", "coef_to_slots"
+ * and "slots_to_coef" (coefficient transposes), "split_digits" (the int8
+ * right-hand-side split of OSHT_PREC_I8X6 / _I8X8 plans).
  * Unknown names return zero launches.  Enabling resets all counters.
  * only_name is copied; NULL times every name.
  */

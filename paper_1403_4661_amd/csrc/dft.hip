@@ -202,16 +202,12 @@ __device__ __forceinline__ void pass_load(cplx* v, const FftCtx& cx) {
 
 // Pass P of an FFT of size 2^LOGM; pb holds its base twiddles (P > 0).
 // The next pass's twiddles are loaded right after this pass's arithmetic,
-// so they arrive while the barriers and the LDS exchange run.  `pre` runs
-// once, before the exchange that precedes the last pass (after pass 0 if
-// there is only one): loads it issues for use after the FFT overlap that
-// pass.
+// so they arrive while the barriers and the LDS exchange run.
 template <bool INV, int LOGM, int P>
 struct FftPass {
   static constexpr int NP = num_passes(LOGM);
   static constexpr int R = pass_radix(LOGM, P);
-  template <class Pre>
-  static __device__ __forceinline__ void run(cplx* v, const FftCtx& cx, const cplx* pb, Pre&& pre) {
+  static __device__ __forceinline__ void run(cplx* v, const FftCtx& cx, const cplx* pb) {
     if constexpr (P > 0) {
       __syncthreads();  // previous pass's stores visible
       pass_load<R>(v, cx);
@@ -222,12 +218,9 @@ struct FftPass {
     if constexpr (P < NP - 1) {
       cplx pn[pass_ntw(LOGM, P + 1)];
       load_twiddles<LOGM, P + 1>(pn, cx);
-      if constexpr (P + 1 == NP - 1) pre();
       __syncthreads();  // all loads of this pass done before stores (in place)
       pass_store<R>(v, cx, 1 << (4 * P));
-      FftPass<INV, LOGM, P + 1>::run(v, cx, pn, pre);
-    } else if constexpr (NP == 1) {
-      pre();
+      FftPass<INV, LOGM, P + 1>::run(v, cx, pn);
     }
   }
 };
@@ -236,13 +229,9 @@ struct FftPass {
 // exit (natural order); the inverse (INV) is the same passes with conjugate
 // twiddles, unscaled.  Every thread of the workgroup must call it (it
 // contains barriers).
-template <bool INV, int LOGM, class Pre>
-__device__ __forceinline__ void fft(cplx* v, const FftCtx& cx, Pre&& pre) {
-  FftPass<INV, LOGM, 0>::run(v, cx, nullptr, pre);
-}
 template <bool INV, int LOGM>
 __device__ __forceinline__ void fft(cplx* v, const FftCtx& cx) {
-  fft<INV, LOGM>(v, cx, [] {});
+  FftPass<INV, LOGM, 0>::run(v, cx, nullptr);
 }
 
 // Workgroup -> pair block, keeping consecutive pair blocks on one XCD
@@ -309,25 +298,19 @@ __global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void chirp_kernel(const Rin
 
 // Shared middle of analysis and synthesis: v holds the chirped input at
 // points t + i T; on return v holds the unscaled convolution at the same
-// points and wo the output chirp w_q (q = t + i T < n, else 0), loaded
-// during the inverse FFT's last pass.  The chirp spectrum is loaded during
-// the forward FFT's last pass.
+// points and wo the output chirp w_q (q = t + i T < n, else 0).
 template <int LOGM>
-__device__ __forceinline__ void bluestein(cplx* v, cplx* wo, const FftCtx& cx,
-                                          const cplx* __restrict__ cf, const cplx* __restrict__ w, int n,
-                                          bool active) {
-  cplx c[RPT];
-  fft<false, LOGM>(v, cx, [&] {});
+__device__ __forceinline__ void bluestein(cplx* v, cplx* wo, const FftCtx& cx, const cplx* __restrict__ cf,
+                                          const cplx* __restrict__ w, int n, bool active) {
+  fft<false, LOGM>(v, cx);
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) c[i] = active ? cf[cx.t + i * cx.T] : cplx{0.0, 0.0};
+  for (int i = 0; i < RPT; ++i) v[i] = cmul(v[i], active ? cf[cx.t + i * cx.T] : cplx{0.0, 0.0});
+  fft<true, LOGM>(v, cx);
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) v[i] = cmul(v[i], c[i]);
-  fft<true, LOGM>(v, cx, [&] {});
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int q = cx.t + i * cx.T;
-      wo[i] = (active && q < n) ? w[q] : cplx{0.0, 0.0};
-    }
+  for (int i = 0; i < RPT; ++i) {
+    const int q = cx.t + i * cx.T;
+    wo[i] = (active && q < n) ? w[q] : cplx{0.0, 0.0};
+  }
 }
 
 struct RingArgs {

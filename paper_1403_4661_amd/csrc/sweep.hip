@@ -781,6 +781,7 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
       gemm_tasks_launch(p, bt + tp[1], tp[2] - tp[1], GemmRole::Correction, "apply_forward_correction", st);
     }
   }
+  ProfScope ps(p.prof, "slots_to_coef", st);
   launch_fwd_scatter(p, p.w_Y.as<double>(), flm, B, st, real_maps);
 }
 
