@@ -84,13 +84,16 @@ __global__ __launch_bounds__(256) void oz_split_a_kernel(const Slot* __restrict_
   const int r = m0 + row;
   const double* Ac = A + sl.offA;
   double mx = 0.0;
+  // out-of-range entries load a valid one and are dropped by a select, so
+  // that the 16 loads of a step are issued together
+  const int rr = min(r, L - 1);
   if (r < L) {
     for (int k0 = 16 * j; k0 < sl.K; k0 += 64) {
       double v[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = k0 + i < sl.K ? fabs(Ac[r + (int64_t)(k0 + i) * sl.ldA]) : 0.0;
+      for (int i = 0; i < 16; ++i) v[i] = fabs(Ac[r + (int64_t)min(k0 + i, sl.K - 1) * sl.ldA]);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) mx = fmax(mx, v[i]);
+      for (int i = 0; i < 16; ++i) mx = fmax(mx, k0 + i < sl.K ? v[i] : 0.0);
     }
   }
   red[row][j] = mx;
@@ -102,10 +105,13 @@ __global__ __launch_bounds__(256) void oz_split_a_kernel(const Slot* __restrict_
     v4i w[S];
 #pragma unroll
     for (int p = 0; p < S; ++p) w[p] = v4i{0, 0, 0, 0};
+    double av[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) av[i] = Ac[rr + (int64_t)min(k0 + i, sl.K - 1) * sl.ldA];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int k = k0 + i;
-      const double v = (r < L && k < sl.K) ? Ac[r + (int64_t)k * sl.ldA] : 0.0;
+      const double v = (r < L && k < sl.K) ? av[i] : 0.0;
       int8_t dg[S];
       digits<S>(ldexp(v, -e), dg);
 #pragma unroll
@@ -143,11 +149,13 @@ __global__ __launch_bounds__(256) void oz_colexp_kernel(const Slot* __restrict__
     double mx = 0.0;
     if (c < ncols) {
       for (int r0 = rc + 16 * j; r0 < rend; r0 += 64) {
+        // rows past the end load row rend - 1 again and are dropped by the
+        // select: a load under a branch is waited for before the next one
         double v[16];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = r0 + i < rend ? fabs(Xs[(int64_t)(r0 + i) * ncols + c]) : 0.0;
+        for (int i = 0; i < 16; ++i) v[i] = fabs(Xs[(int64_t)min(r0 + i, rend - 1) * ncols + c]);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) mx = fmax(mx, v[i]);
+        for (int i = 0; i < 16; ++i) mx = fmax(mx, r0 + i < rend ? v[i] : 0.0);
       }
     }
     red[cl][j] = mx;
@@ -176,14 +184,21 @@ __global__ __launch_bounds__(256) void oz_split_x_kernel(const Slot* __restrict_
     const int c = c0 + cl;
     int e = c < ncols ? Xexp[(int64_t)slot * Np + c] : 0;
     if (e == INT_MIN) e = 0;  // an all-zero column
+    const int cc = min(c, ncols - 1);  // padding columns load column ncols - 1 and drop it
     for (int r0 = rc + 16 * j; r0 < rend; r0 += 64) {
       v4i w[S];
 #pragma unroll
       for (int p = 0; p < S; ++p) w[p] = v4i{0, 0, 0, 0};
+      // all 16 loads issued before any is used (a load under a branch is
+      // waited for before the next one); rows past K load row K - 1 and are
+      // dropped by the select
+      double xv[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) xv[i] = Xs[(int64_t)min(r0 + i, K - 1) * ncols + cc];
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const int r = r0 + i;
-        const double v = (c < ncols && r < K) ? Xs[(int64_t)r * ncols + c] : 0.0;
+        const double v = (c < ncols && r < K) ? xv[i] : 0.0;
         int8_t dg[S];
         digits<S>(ldexp(v, -e), dg);
 #pragma unroll
@@ -193,6 +208,71 @@ __global__ __launch_bounds__(256) void oz_split_x_kernel(const Slot* __restrict_
       for (int p = 0; p < S; ++p)
         *reinterpret_cast<v4i*>(out + (int64_t)p * Np * Kx + (int64_t)c * Kx + r0) = w[p];
     }
+  }
+}
+
+// The exponents and digits of the right-hand side in one pass, for up to
+// 512 NCH rows (L <= 1024 with NCH = 2, L <= 2048 with NCH = 4): one
+// workgroup per (slot, 8 columns), thread (column c = t % 8, q = t / 8)
+// holding rows [16 (q + 32 i), +16), i < NCH, in registers.  The column
+// maximum comes from those registers and an LDS reduction, then the same
+// registers are split, so X is read from HBM once (the two-kernel path
+// above reads it twice).  Exponents and digits are those of that path: an
+// all-zero column stores exponent 0.
+template <int S, int NCH>
+__global__ __launch_bounds__(256) void oz_xsplit_kernel(const Slot* __restrict__ slots, const double* __restrict__ X,
+                                                        int L, int ncols, int Np, int Kx, int8_t* __restrict__ X8,
+                                                        int32_t* __restrict__ Xexp) {
+  __shared__ double red[32][8];
+  __shared__ int ecol[8];
+  const int slot = blockIdx.x, cl = threadIdx.x & 7, q = threadIdx.x >> 3;
+  const int c = blockIdx.y * 8 + cl;
+  const int K = slots[slot].K, Kp = (K + 63) / 64 * 64;
+  const double* Xs = X + (int64_t)slot * L * ncols;
+  const int cc = min(c, ncols - 1);  // padding columns load column ncols - 1 and drop it
+  double v[NCH][16];
+  // every load issued before any is used; rows past K load row K - 1
+#pragma unroll
+  for (int i = 0; i < NCH; ++i)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[i][j] = Xs[(int64_t)min(16 * (q + 32 * i) + j, K - 1) * ncols + cc];
+  double mx = 0.0;
+#pragma unroll
+  for (int i = 0; i < NCH; ++i)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const bool ok = c < ncols && 16 * (q + 32 * i) + j < K;
+      v[i][j] = ok ? v[i][j] : 0.0;
+      mx = fmax(mx, fabs(v[i][j]));
+    }
+  red[q][cl] = mx;
+  __syncthreads();
+  if (q == 0) {
+    double m = 0.0;
+    for (int i = 0; i < 32; ++i) m = fmax(m, red[i][cl]);
+    const int e = exp_above(m);
+    ecol[cl] = e;
+    Xexp[(int64_t)slot * Np + c] = e;
+  }
+  __syncthreads();
+  const int e = ecol[cl];
+  int8_t* out = X8 + (int64_t)slot * S * Np * Kx + (int64_t)c * Kx;
+#pragma unroll
+  for (int i = 0; i < NCH; ++i) {
+    const int r0 = 16 * (q + 32 * i);
+    if (r0 >= Kp) continue;
+    v4i w[S];
+#pragma unroll
+    for (int p = 0; p < S; ++p) w[p] = v4i{0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      int8_t dg[S];
+      digits<S>(ldexp(v[i][j], -e), dg);
+#pragma unroll
+      for (int p = 0; p < S; ++p) w[p][j >> 2] |= (int)(uint8_t)dg[p] << (8 * (j & 3));
+    }
+#pragma unroll
+    for (int p = 0; p < S; ++p) *reinterpret_cast<v4i*>(out + (int64_t)p * Np * Kx + r0) = w[p];
   }
 }
 
@@ -392,6 +472,16 @@ void oz_descs(const Plan& p, int64_t B, const double* Y, int8_t* X8, const int32
 
 void launch_oz_split_x(const Plan& p, const double* X, int64_t B, int8_t* X8, int32_t* Xexp, hipStream_t st) {
   const int ncols = p.ncols_per_map * (int)B, Np = oz_x_cols(p, B), Kx = oz_x_ld(p);
+  if (Kx <= 2048) {  // one pass, the slot's rows of 8 columns in registers
+    const dim3 grid((unsigned)p.nslots, (unsigned)(Np / 8));
+    auto go1 = [&](auto kernel) {
+      hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, p.d_slots.as<Slot>(), X, p.L, ncols, Np, Kx, X8, Xexp);
+    };
+    if (p.oz == 6) Kx <= 1024 ? go1(oz_xsplit_kernel<6, 2>) : go1(oz_xsplit_kernel<6, 4>);
+    else Kx <= 1024 ? go1(oz_xsplit_kernel<8, 2>) : go1(oz_xsplit_kernel<8, 4>);
+    OSHT_HIP(hipGetLastError());
+    return;
+  }
   const int64_t ne = (int64_t)p.nslots * Np;
   hipLaunchKernelGGL(oz_fill_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(ne, 256), 1024)), dim3(256), 0, st, Xexp,
                      ne, (int32_t)INT_MIN);

@@ -10,7 +10,7 @@ the checks are properties that hold at any size:
     3e-13 for 512 <= |m| < 1024, 5e-11 for 256 <= |m| < 512 and up to
     6e-5 for |m| < 256 (the FP64 oracle shows the same growth);
   * the FP32 plan (OSHT_PREC_FP32_FWD) agrees with the FP64 plan to 1e-6 in
-    both directions.
+    both directions, and the int8-digit inverse (OSHT_PREC_I8X6) to 1e-8.
 Element by element against the oracle: map 0's samples on four rings --
 the ring nearest numerator 370 (theta ~ 0.284, where seeds of orders
 m ~ 560 underflow FP64 and the recursion rescales, Sec. III-F), the rings
@@ -108,6 +108,21 @@ def test_L2048_fp32_matches_fp64():
     # the FP64 alias chain is shared
     g32 = to_host(p32.forward(to_dev(f64)))
     assert relmax(g32, back64) < 1e-6
+
+
+def test_L2048_int8_inverse_vs_oracle_and_fp64():
+    """OSHT_PREC_I8X6 at L = 2048: right-hand-side columns of up to 2048 rows,
+    which the one-pass digit split holds as four 16-row chunks per thread.
+    Against the stored oracle rings and the FP64 plan's inverse of every
+    sample, <= 1e-8."""
+    _release("fp32-fwd")
+    if "f64" not in _cache:
+        pytest.skip("needs the FP64 results of the first test")
+    f64, _ = _cache["f64"]
+    fi = to_host(_plan("i8x6").inverse(to_dev(_flm())))
+    _release("i8x6")
+    assert _ring_error(fi[0], 0) < 1e-8
+    assert relmax(fi, f64) < 1e-8
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32-fwd", 1e-6)])
