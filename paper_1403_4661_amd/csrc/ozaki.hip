@@ -325,6 +325,14 @@ __global__ __launch_bounds__(256) void oz_apply_kernel(const OzDesc* __restrict_
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
     for (int dd = 0; dd < S; ++dd) acc[cb][dd] = v4i{0, 0, 0, 0};
+  // the epilogue's row and column exponents, loaded before the k loop
+  // (clamped indices; the unused ones are dropped): guarded one by one in
+  // the epilogue, each was waited for in turn after the last product
+  int ear[4], xe[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) ear[v] = ((gi32_ptr)d.ea)[min(m0 + 16 * wave + 4 * kq + v, d.M - 1)];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) xe[cb] = ((gi32_ptr)d.xe)[min(n0 + cb * 16 + li, d.N - 1)];
   const int nk = d.Kp / 64;
   v4i a[S], an[S], an2[S], an3[S], bt[S];
   if (nk > 0) {
@@ -372,19 +380,18 @@ __global__ __launch_bounds__(256) void oz_apply_kernel(const OzDesc* __restrict_
       if (PF >= 3) an2[p] = an3[p];
     }
   }
-  gi32_ptr ea = (gi32_ptr)d.ea;
   gf64_ptr Cg = (gf64_ptr)d.C;
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
     const int col = n0 + cb * 16 + li;
     if (col >= d.N) continue;
-    int fe = ((gi32_ptr)d.xe)[col];
+    int fe = xe[cb];
     if (fe == INT_MIN) fe = 0;  // an all-zero column (its digits and products are zero)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = m0 + 16 * wave + 4 * kq + v;
       if (r < d.M) {
-        const int e = ea[r] + fe;
+        const int e = ear[v] + fe;
         double y = 0.0;
 #pragma unroll
         for (int dd = 0; dd < S; ++dd) y += ldexp((double)acc[cb][dd][v], e - 7 * (dd + 2));
