@@ -17,9 +17,12 @@
 // emulation at L = 256: 2e-8 with 5 digits, 2e-10 with 6, 2e-12 with 7,
 // relative to max |f|); FP32 operands give 4e-8.
 //
-// Layouts.  A digits (plan): per slot, plane p at offA8 + p * Mp * Kp, row i
-// at i * Kp (k contiguous), Mp = L rounded up to 64, Kp = K rounded up to 64,
-// zero padded; e_i at Aexp[slot * Mp + i].  X digits (per call): per slot,
+// Layouts.  A digits (plan): per slot, plane p at offA8 + p * Mp * Kp, Mp = L
+// rounded up to 64, Kp = K rounded up to 64, zero padded, in 1 KB blocks of
+// 16 rows x 64 k (k contiguous within a row): block (i / 16, k / 64) at
+// ((i / 16) (Kp / 64) + k / 64) * 1024, entry (i % 16) * 64 + k % 64, so one
+// wave's load of a k step (16 rows x 64 bytes) is one contiguous kilobyte;
+// e_i at Aexp[slot * Mp + i].  X digits (per call): per slot,
 // plane q at slot * S * Np * Kx + q * Np * Kx, column c at c * Kx, Np = the
 // slot columns rounded up to 64, Kx = L rounded up to 64; f_c at
 // Xexp[slot * Np + c].
@@ -118,7 +121,9 @@ __global__ __launch_bounds__(256) void oz_split_a_kernel(const Slot* __restrict_
       for (int p = 0; p < S; ++p) w[p][i >> 2] |= (int)(uint8_t)dg[p] << (8 * (i & 3));
     }
 #pragma unroll
-    for (int p = 0; p < S; ++p) *reinterpret_cast<v4i*>(out + (int64_t)p * Mp * Kp + (int64_t)r * Kp + k0) = w[p];
+    for (int p = 0; p < S; ++p)
+      *reinterpret_cast<v4i*>(out + (int64_t)p * Mp * Kp + ((int64_t)(r >> 4) * (Kp >> 6) + (k0 >> 6)) * 1024 +
+                              (r & 15) * 64 + (k0 & 63)) = w[p];
   }
 }
 
@@ -314,8 +319,10 @@ __global__ __launch_bounds__(256) void oz_apply_kernel(const OzDesc* __restrict_
   const int m0 = tk.mt * kOzTile, n0 = tk.nt * kOzTile;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int li = lane & 15, kq = lane >> 4;
-  // this lane's A chunk: row m0 + 16 wave + li, bytes [16 kq, 16 kq + 16) of each 64-deep step
-  gv4i_ptr asrc = (gv4i_ptr)(d.A + (int64_t)(m0 + 16 * wave + li) * d.Kp + 16 * kq);
+  const int nk = d.Kp / 64;
+  // this lane's A chunk: row m0 + 16 wave + li, bytes [16 kq, 16 kq + 16) of
+  // each 64-deep step, in the 1 KB block of its 16 rows (steps 1 KB apart)
+  gv4i_ptr asrc = (gv4i_ptr)(d.A + ((int64_t)((m0 >> 4) + wave) * nk) * 1024 + li * 64 + 16 * kq);
   // this thread's B chunk: column n0 + (t >> 2), bytes [16 (t & 3), +16)
   const int bc = t >> 2, bch = t & 3;
   gv4i_ptr bsrc = (gv4i_ptr)(d.X + (int64_t)(n0 + bc) * d.ldX + 16 * bch);
@@ -333,12 +340,11 @@ __global__ __launch_bounds__(256) void oz_apply_kernel(const OzDesc* __restrict_
   for (int v = 0; v < 4; ++v) ear[v] = ((gi32_ptr)d.ea)[min(m0 + 16 * wave + 4 * kq + v, d.M - 1)];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) xe[cb] = ((gi32_ptr)d.xe)[min(n0 + cb * 16 + li, d.N - 1)];
-  const int nk = d.Kp / 64;
   v4i a[S], an[S], an2[S], an3[S], bt[S];
   if (nk > 0) {
     oz_load<S>(asrc, d.planeA, a);
-    if (PF >= 2) oz_load<S>(asrc + min(1, nk - 1) * 4, d.planeA, an);
-    if (PF >= 3) oz_load<S>(asrc + min(2, nk - 1) * 4, d.planeA, an2);
+    if (PF >= 2) oz_load<S>(asrc + min(1, nk - 1) * 64, d.planeA, an);
+    if (PF >= 3) oz_load<S>(asrc + min(2, nk - 1) * 64, d.planeA, an2);
     oz_load<S>(bsrc, d.planeX, bt);
 #pragma unroll
     for (int p = 0; p < S; ++p) *reinterpret_cast<v4i*>(&bs[0][p][bpos]) = bt[p];
@@ -346,7 +352,7 @@ __global__ __launch_bounds__(256) void oz_apply_kernel(const OzDesc* __restrict_
   for (int kt = 0; kt < nk; ++kt) {
     // A digits PF steps ahead and the next step's B digits (past the last
     // step the last one is reloaded, so every path issues the same loads)
-    oz_load<S>(asrc + min(kt + PF, nk - 1) * 4, d.planeA, PF == 3 ? an3 : PF == 2 ? an2 : an);
+    oz_load<S>(asrc + min(kt + PF, nk - 1) * 64, d.planeA, PF == 3 ? an3 : PF == 2 ? an2 : an);
     oz_load<S>(bsrc + min(kt + 1, nk - 1) * 4, d.planeX, bt);
     __syncthreads();  // B tile of step kt stored by every thread
     const char* st = bs[kt & 1][0];
