@@ -22,10 +22,12 @@
 // 16 rows x 64 k (k contiguous within a row): block (i / 16, k / 64) at
 // ((i / 16) (Kp / 64) + k / 64) * 1024, entry (i % 16) * 64 + k % 64, so one
 // wave's load of a k step (16 rows x 64 bytes) is one contiguous kilobyte;
-// e_i at Aexp[slot * Mp + i].  X digits (per call): per slot,
-// plane q at slot * S * Np * Kx + q * Np * Kx, column c at c * Kx, Np = the
-// slot columns rounded up to 64, Kx = L rounded up to 64; f_c at
-// Xexp[slot * Np + c].
+// e_i at Aexp[slot * Mp + i].  X digits (per call): per slot, plane q at
+// slot * S * Np * Kx + q * Np * Kx, Np = the slot columns rounded up to 64,
+// Kx = L rounded up to 64, in 4 KB blocks of 64 columns x 64 k (k contiguous
+// within a column): block (c / 64, k / 64) at ((c / 64) (Kx / 64) + k / 64)
+// * 4096, entry (c % 64) * 64 + k % 64 -- a workgroup's k step of B is one
+// contiguous block; f_c at Xexp[slot * Np + c].
 //
 // GEMM: one workgroup (4 waves) per 64 x 64 tile of Y; wave w owns rows
 // [16w, 16w + 16) and all 64 columns as four 16 x 16 blocks with S int32
@@ -64,6 +66,11 @@ __device__ __forceinline__ void digits(double r, int8_t* out) {
 }
 
 // exponent e with |v| < 2^e (0 for v = 0)
+// Offset of digit (column c, k) within one plane of the blocked X layout.
+__device__ __forceinline__ int64_t xblk(int c, int k, int Kx) {
+  return ((int64_t)(c >> 6) * (Kx >> 6) + (k >> 6)) * 4096 + (c & 63) * 64 + (k & 63);
+}
+
 __device__ __forceinline__ int exp_above(double v) {
   int e = 0;
   if (v != 0.0) (void)frexp(v, &e);
@@ -211,7 +218,7 @@ __global__ __launch_bounds__(256) void oz_split_x_kernel(const Slot* __restrict_
       }
 #pragma unroll
       for (int p = 0; p < S; ++p)
-        *reinterpret_cast<v4i*>(out + (int64_t)p * Np * Kx + (int64_t)c * Kx + r0) = w[p];
+        *reinterpret_cast<v4i*>(out + (int64_t)p * Np * Kx + xblk(c, r0, Kx)) = w[p];
     }
   }
 }
@@ -261,7 +268,7 @@ __global__ __launch_bounds__(256) void oz_xsplit_kernel(const Slot* __restrict__
   }
   __syncthreads();
   const int e = ecol[cl];
-  int8_t* out = X8 + (int64_t)slot * S * Np * Kx + (int64_t)c * Kx;
+  int8_t* out = X8 + (int64_t)slot * S * Np * Kx;
 #pragma unroll
   for (int i = 0; i < NCH; ++i) {
     const int r0 = 16 * (q + 32 * i);
@@ -277,7 +284,7 @@ __global__ __launch_bounds__(256) void oz_xsplit_kernel(const Slot* __restrict__
       for (int p = 0; p < S; ++p) w[p][j >> 2] |= (int)(uint8_t)dg[p] << (8 * (j & 3));
     }
 #pragma unroll
-    for (int p = 0; p < S; ++p) *reinterpret_cast<v4i*>(out + (int64_t)p * Np * Kx + r0) = w[p];
+    for (int p = 0; p < S; ++p) *reinterpret_cast<v4i*>(out + (int64_t)p * Np * Kx + xblk(c, r0, Kx)) = w[p];
   }
 }
 
@@ -325,7 +332,8 @@ __global__ __launch_bounds__(256) void oz_apply_kernel(const OzDesc* __restrict_
   gv4i_ptr asrc = (gv4i_ptr)(d.A + ((int64_t)((m0 >> 4) + wave) * nk) * 1024 + li * 64 + 16 * kq);
   // this thread's B chunk: column n0 + (t >> 2), bytes [16 (t & 3), +16)
   const int bc = t >> 2, bch = t & 3;
-  gv4i_ptr bsrc = (gv4i_ptr)(d.X + (int64_t)(n0 + bc) * d.ldX + 16 * bch);
+  // (steps 4 KB apart in the column tile's blocks)
+  gv4i_ptr bsrc = (gv4i_ptr)(d.X + xblk(n0 + bc, 16 * bch, d.ldX));
   const int bpos = bc * 64 + 16 * (bch ^ ((bc >> 2) & 3));
   v4i acc[4][S];
 #pragma unroll
@@ -353,7 +361,7 @@ __global__ __launch_bounds__(256) void oz_apply_kernel(const OzDesc* __restrict_
     // A digits PF steps ahead and the next step's B digits (past the last
     // step the last one is reloaded, so every path issues the same loads)
     oz_load<S>(asrc + min(kt + PF, nk - 1) * 64, d.planeA, PF == 3 ? an3 : PF == 2 ? an2 : an);
-    oz_load<S>(bsrc + min(kt + 1, nk - 1) * 4, d.planeX, bt);
+    oz_load<S>(bsrc + min(kt + 1, nk - 1) * 256, d.planeX, bt);
     __syncthreads();  // B tile of step kt stored by every thread
     const char* st = bs[kt & 1][0];
     // B fragments of column block cb + 1 are read from LDS while the
