@@ -223,22 +223,24 @@ __global__ __launch_bounds__(256) void oz_split_x_kernel(const Slot* __restrict_
   }
 }
 
-// The exponents and digits of the right-hand side in one pass, for up to
-// 512 NCH rows (L <= 1024 with NCH = 2, L <= 2048 with NCH = 4): one
-// workgroup per (slot, 8 columns), thread (column c = t % 8, q = t / 8)
-// holding rows [16 (q + 32 i), +16), i < NCH, in registers.  The column
-// maximum comes from those registers and an LDS reduction, then the same
-// registers are split, so X is read from HBM once (the two-kernel path
-// above reads it twice).  Exponents and digits are those of that path: an
-// all-zero column stores exponent 0.
-template <int S, int NCH>
+// The exponents and digits of the right-hand side in one pass: one
+// workgroup per (slot, CW columns), thread (column c = t % CW, q = t / CW)
+// holding rows [16 (q + NQ i), +16), i < NCH, NQ = 256 / CW, in registers,
+// so 16 NQ NCH rows at most (CW = 16, NCH = 4: L <= 1024; CW = 8, NCH = 4:
+// L <= 2048).  CW = 16 reads whole 128-byte row pieces (CW = 8 fetched each
+// line twice).  The column maximum comes from those registers and an LDS
+// reduction, then the same registers are split, so X is read from HBM once
+// (the two-kernel path above reads it twice).  Exponents and digits are
+// those of that path: an all-zero column stores exponent 0.
+template <int S, int CW, int NCH>
 __global__ __launch_bounds__(256) void oz_xsplit_kernel(const Slot* __restrict__ slots, const double* __restrict__ X,
                                                         int L, int ncols, int Np, int Kx, int8_t* __restrict__ X8,
                                                         int32_t* __restrict__ Xexp) {
-  __shared__ double red[32][8];
-  __shared__ int ecol[8];
-  const int slot = blockIdx.x, cl = threadIdx.x & 7, q = threadIdx.x >> 3;
-  const int c = blockIdx.y * 8 + cl;
+  constexpr int NQ = 256 / CW;
+  __shared__ double red[NQ][CW];
+  __shared__ int ecol[CW];
+  const int slot = blockIdx.x, cl = threadIdx.x % CW, q = threadIdx.x / CW;
+  const int c = blockIdx.y * CW + cl;
   const int K = slots[slot].K, Kp = (K + 63) / 64 * 64;
   const double* Xs = X + (int64_t)slot * L * ncols;
   const int cc = min(c, ncols - 1);  // padding columns load column ncols - 1 and drop it
@@ -247,13 +249,13 @@ __global__ __launch_bounds__(256) void oz_xsplit_kernel(const Slot* __restrict__
 #pragma unroll
   for (int i = 0; i < NCH; ++i)
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[i][j] = Xs[(int64_t)min(16 * (q + 32 * i) + j, K - 1) * ncols + cc];
+    for (int j = 0; j < 16; ++j) v[i][j] = Xs[(int64_t)min(16 * (q + NQ * i) + j, K - 1) * ncols + cc];
   double mx = 0.0;
 #pragma unroll
   for (int i = 0; i < NCH; ++i)
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const bool ok = c < ncols && 16 * (q + 32 * i) + j < K;
+      const bool ok = c < ncols && 16 * (q + NQ * i) + j < K;
       v[i][j] = ok ? v[i][j] : 0.0;
       mx = fmax(mx, fabs(v[i][j]));
     }
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(256) void oz_xsplit_kernel(const Slot* __restrict__
   __syncthreads();
   if (q == 0) {
     double m = 0.0;
-    for (int i = 0; i < 32; ++i) m = fmax(m, red[i][cl]);
+    for (int i = 0; i < NQ; ++i) m = fmax(m, red[i][cl]);
     const int e = exp_above(m);
     ecol[cl] = e;
     Xexp[(int64_t)slot * Np + c] = e;
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(256) void oz_xsplit_kernel(const Slot* __restrict__
   int8_t* out = X8 + (int64_t)slot * S * Np * Kx;
 #pragma unroll
   for (int i = 0; i < NCH; ++i) {
-    const int r0 = 16 * (q + 32 * i);
+    const int r0 = 16 * (q + NQ * i);
     if (r0 >= Kp) continue;
     v4i w[S];
 #pragma unroll
@@ -493,13 +495,14 @@ void oz_descs(const Plan& p, int64_t B, const double* Y, int8_t* X8, const int32
 
 void launch_oz_split_x(const Plan& p, const double* X, int64_t B, int8_t* X8, int32_t* Xexp, hipStream_t st) {
   const int ncols = p.ncols_per_map * (int)B, Np = oz_x_cols(p, B), Kx = oz_x_ld(p);
-  if (Kx <= 2048) {  // one pass, the slot's rows of 8 columns in registers
-    const dim3 grid((unsigned)p.nslots, (unsigned)(Np / 8));
+  if (Kx <= 2048) {  // one pass, a slot's rows of 16 (L <= 1024) or 8 columns in registers
+    const int cw = Kx <= 1024 ? 16 : 8;
+    const dim3 grid((unsigned)p.nslots, (unsigned)(Np / cw));
     auto go1 = [&](auto kernel) {
       hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, p.d_slots.as<Slot>(), X, p.L, ncols, Np, Kx, X8, Xexp);
     };
-    if (p.oz == 6) Kx <= 1024 ? go1(oz_xsplit_kernel<6, 2>) : go1(oz_xsplit_kernel<6, 4>);
-    else Kx <= 1024 ? go1(oz_xsplit_kernel<8, 2>) : go1(oz_xsplit_kernel<8, 4>);
+    if (p.oz == 6) cw == 16 ? go1(oz_xsplit_kernel<6, 16, 4>) : go1(oz_xsplit_kernel<6, 8, 4>);
+    else cw == 16 ? go1(oz_xsplit_kernel<8, 16, 4>) : go1(oz_xsplit_kernel<8, 8, 4>);
     OSHT_HIP(hipGetLastError());
     return;
   }
