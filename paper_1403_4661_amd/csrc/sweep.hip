@@ -269,6 +269,10 @@ __global__ __launch_bounds__(512) void delta_solve_kernel(Geo g, int u0, int nu,
 // triangle) into equal chunks, and the partial tiles are summed in LDS in
 // wave order.  Writes delta into D[slot][r][col].
 constexpr int kDeltaWaves = 16;
+// Workgroups per 16-row tile, each over one part of the sources (1 or 2):
+// the kernel is bound by its chain of dependent loads, so halving each
+// wave's share of the sources shortens it.
+constexpr int kDeltaSplit = 2;
 __global__ __launch_bounds__(64 * kDeltaWaves) void delta_apply_kernel(
     Geo g, int u0, int nu, int s0, const int32_t* __restrict__ src_ptr, const int32_t* __restrict__ src_yrow,
     const double* __restrict__ Minv, int ld, const double* __restrict__ Y, const int32_t* __restrict__ unk_slot,
@@ -279,8 +283,13 @@ __global__ __launch_bounds__(64 * kDeltaWaves) void delta_apply_kernel(
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row0 = blockIdx.x * 16, col0 = blockIdx.y * 32;
   const int kt = src_ptr[u0 + min(nu, row0 + 16)] - s0;
-  const int chunk = ((kt + kDeltaWaves - 1) / kDeltaWaves + 3) & ~3;
-  const int kb = wave * chunk, ke = min(kt, kb + chunk);
+  // with gridDim.z = 2 each workgroup takes one half of the sources and the
+  // two partial tiles are added into the zeroed D: two addends onto zero
+  // give the same bits in either order
+  const int kh = (kt + 1) / 2;
+  const int zb = gridDim.z > 1 ? (int)blockIdx.z * kh : 0, ze = gridDim.z > 1 ? min(kt, zb + kh) : kt;
+  const int chunk = ((ze - zb + kDeltaWaves - 1) / kDeltaWaves + 3) & ~3;
+  const int kb = zb + wave * chunk, ke = min(ze, kb + chunk);
   const int r = row0 + (lane & 15), q = lane >> 4;
   const int c0 = col0 + (lane & 15), c1 = c0 + 16;
   const bool rok = r < nu, c0ok = c0 < J, c1ok = c1 < J;
@@ -347,7 +356,9 @@ __global__ __launch_bounds__(64 * kDeltaWaves) void delta_apply_kernel(
     const int ul = row0 + i, j = col0 + 16 * ct + c;
     if (ul < nu && j < J) {
       const int u = u0 + ul;
-      D[((int64_t)unk_slot[u] * bD + unk_r[u]) * g.ncols + order_col(g, unk_m[u], j)] = sum;
+      double* dp = D + ((int64_t)unk_slot[u] * bD + unk_r[u]) * g.ncols + order_col(g, unk_m[u], j);
+      if (gridDim.z > 1) unsafeAtomicAdd(dp, sum);
+      else *dp = sum;
     }
   }
 }
@@ -762,7 +773,7 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
       if (fb.dense) {
         ProfScope ps(p.prof, "delta_solve", st);
         const int J = 2 * (int)B;
-        hipLaunchKernelGGL(delta_apply_kernel, dim3((unsigned)ceil_div(nu, 16), (unsigned)ceil_div(J, 32)),
+        hipLaunchKernelGGL(delta_apply_kernel, dim3((unsigned)ceil_div(nu, 16), (unsigned)ceil_div(J, 32), kDeltaSplit),
                            dim3(64 * kDeltaWaves), 0, st, g, u0, nu, fb.src_ptr[u0], fb.d_src_ptr.as<int32_t>(),
                            fb.d_src_yrow.as<int32_t>(), fb.d_minv.as<double>() + fb.minv_off[blk], fb.minv_ld[blk],
                            p.w_Y.as<double>(), fb.d_unk_slot.as<int32_t>(), fb.d_unk_r.as<int32_t>(),
