@@ -56,6 +56,11 @@ __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.x + b.x, a.y + 
 __device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.x - b.x, a.y - b.y}; }
 
 constexpr int RPT = 16;  // points per thread
+// M >= 2n - 1 with M even gives n <= M/2: the points t + i T with
+// i >= RH = RPT/2 lie at or past M/2 and so past every ring of the class.
+// They enter the first FFT as zeros and leave the last one unread, so no
+// load, chirp product or store touches them.
+constexpr int RH = RPT / 2;
 
 // e^{-2 pi i j/16} (forward); the inverse uses the conjugate.
 __device__ __forceinline__ cplx w16(int j, bool inv) {
@@ -297,15 +302,19 @@ __global__ __launch_bounds__(LOGM == 13 ? 512 : 256) void chirp_kernel(const Rin
 }
 
 // Shared middle of analysis and synthesis: v holds the chirped input at
-// points t + i T; on return v holds the unscaled convolution at the same
-// points and wo the output chirp w_q (q = t + i T < n, else 0).
+// points t + i T (zero for i >= RH); on return v holds the unscaled
+// convolution at the same points and wo[i], i < RH, the output chirp w_q
+// (q = t + i T < n, else 0).
 // BATCH: the chirp-spectrum and output-chirp loads are issued together and
 // selected after (a load under a branch is waited for before the next one
 // is issued; cf of an inactive pair is its ring's, and positions past the
 // ring load its last chirp value).  Measured per direction at L = 1024,
 // B = 16, with the input loads batched as well: analysis 391 -> 385 us with
 // it, synthesis 370 -> 378 us (its registers spill), so only the analysis
-// batches them.  The two directions together went 0.80 -> 0.76 ms.
+// batches them.  The two directions together went 0.80 -> 0.76 ms.  With the
+// upper half of each thread's points left out of the loads and stores
+// (RH), neither direction spills; batching the synthesis then gains
+// nothing (347 us either way) and moves its rounding, so it stays unbatched.
 template <int LOGM, bool BATCH>
 __device__ __forceinline__ void bluestein(cplx* v, cplx* wo, const FftCtx& cx, const cplx* __restrict__ cf,
                                           const cplx* __restrict__ w, int n, bool active) {
@@ -323,13 +332,13 @@ __device__ __forceinline__ void bluestein(cplx* v, cplx* wo, const FftCtx& cx, c
   fft<true, LOGM>(v, cx);
   if constexpr (BATCH) {
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) wo[i] = w[min(cx.t + i * cx.T, n - 1)];
+    for (int i = 0; i < RH; ++i) wo[i] = w[min(cx.t + i * cx.T, n - 1)];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i)
+    for (int i = 0; i < RH; ++i)
       if (!(active && cx.t + i * cx.T < n)) wo[i] = cplx{0.0, 0.0};
   } else {
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
+    for (int i = 0; i < RH; ++i) {
       const int q = cx.t + i * cx.T;
       wo[i] = (active && q < n) ? w[q] : cplx{0.0, 0.0};
     }
@@ -381,35 +390,39 @@ __device__ __forceinline__ void analysis_body(const RingArgs& a, int k0, int npa
   const double* fb = fa + (int64_t)L * L;
   const bool has_b = 2 * pc.b + 1 < Breal;
   const double* fbs = has_b ? fb : fa;  // a missing second real map reads the first and drops it
-  cplx v[RPT], ws[RPT];
+  cplx v[RPT], ws[RH];
   // every load issued before any is used: positions past the ring (and
   // every position of an inactive pair, whose ring is k0) load the ring's
   // last sample, which the select drops
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
+  for (int i = 0; i < RH; ++i) {
     const int p = min(t + i * T, pc.n - 1);
     if constexpr (REAL) v[i] = cplx{fa[p], fbs[p]};
     else v[i] = fr[p];
     ws[i] = w[p];
   }
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
+  for (int i = 0; i < RH; ++i) {
     cplx x = v[i];
     if constexpr (REAL) {
       if (!has_b) x.y = 0.0;
     }
     v[i] = (pc.active && t + i * T < pc.n) ? cmul(x, ws[i]) : cplx{0.0, 0.0};
   }
-  cplx wo[RPT];
+#pragma unroll
+  for (int i = RH; i < RPT; ++i) v[i] = cplx{0.0, 0.0};
+  cplx wo[RH];
   bluestein<LOGM, true>(v, wo, cx, chirp_fft + pc.off, w, pc.n, pc.active);
   if (pc.active) {
     const double sc = (normalise ? 1.0 / pc.n : 1.0) / M;
+    cplx* Ht = H + (pc.base + t) * B + pc.b;
+    const int64_t hs = (int64_t)T * B;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
+    for (int i = 0; i < RH; ++i) {
       const int q = t + i * T;
       if (q < pc.n) {
         const cplx c = cmul(v[i], wo[i]);
-        H[(pc.base + q) * B + pc.b] = {c.x * sc, c.y * sc};
+        Ht[i * hs] = {c.x * sc, c.y * sc};
       }
     }
   }
@@ -483,16 +496,18 @@ __device__ __forceinline__ void synthesis_body(const RingArgs& a, int k0, int np
   const int t = threadIdx.x % T;
   FftCtx cx{lds_buf + (threadIdx.x / T) * (M + M / 16), tw, logM, logMmax, t, T};
   const cplx* w = chirp_tab + pc.base;
-  cplx v[RPT], ws[RPT];
+  cplx v[RPT], ws[RH];
   // loads first (clamped to the ring's last bin), selects after
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
+  for (int i = 0; i < RH; ++i) {
     const int q = min(t + i * T, pc.n - 1);
     v[i] = H[(pc.base + q) * B + pc.b];
     ws[i] = w[q];
   }
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
+  for (int i = RH; i < RPT; ++i) v[i] = cplx{0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < RH; ++i) {
     cplx h = {0.0, 0.0};
     if (pc.active && t + i * T < pc.n) {
       h = v[i];
@@ -501,7 +516,7 @@ __device__ __forceinline__ void synthesis_body(const RingArgs& a, int k0, int np
     }
     v[i] = h;
   }
-  cplx wo[RPT];
+  cplx wo[RH];
   bluestein<LOGM, false>(v, wo, cx, chirp_fft + pc.off, w, pc.n, pc.active);
   if (pc.active) {
     const double sc = 1.0 / M;
@@ -511,7 +526,7 @@ __device__ __forceinline__ void synthesis_body(const RingArgs& a, int k0, int np
     double* fb = fa + (int64_t)L * L;
     const bool has_b = 2 * pc.b + 1 < Breal;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
+    for (int i = 0; i < RH; ++i) {
       const int j = t + i * T;
       if (j < pc.n) {
         const cplx c = cmul(v[i], wo[i]);
