@@ -89,13 +89,17 @@ __global__ __launch_bounds__(256) void block_gather_kernel(Geo g, const Slot* __
   X[((int64_t)slot * g.L + r) * nc + cc] = v;
 }
 
-// The rows of small rings (k < kthr) alias ~(2L-1)/n_k solved orders each.
+// The rows of small rings (k < kthr) alias up to ~(2L-1)/n_k solved orders.
 // One workgroup of 1024 threads per (slot, row): threads split the columns
 // and, for each column, the alias list into C interleaved chunks whose
 // partial sums are reduced in a fixed order through LDS.  Each thread keeps
 // four alias loads in flight (an excluded order loads Y[0] instead and is
 // dropped by a select).
 constexpr int kWideThreads = 1024;
+// Rings with more aliased orders per bin than this go to the wide kernel: a
+// block-gather thread then walks at most 8 batches of four alias loads
+// (32 and 16 measured equal, 64 slower by 0.6 us per block at L = 1024).
+constexpr int kWideAliases = 32;
 __global__ __launch_bounds__(kWideThreads) void wide_gather_kernel(Geo g, const Slot* __restrict__ slots,
                                                                    const int32_t* __restrict__ wide_slot,
                                                                    const int32_t* __restrict__ wide_row, int q1,
@@ -584,9 +588,10 @@ void build_fwd_blocks(Plan& p, int b) {
   fb.w_ptr.push_back(0);
   fb.wt_ptr.push_back(0);
   fb.wide_ptr.push_back(0);
-  // rings with more than ~64 aliased orders per bin: n_k * 64 < 2L - 1
+  // rings with more than ~kWideAliases aliased orders per bin:
+  // n_k * kWideAliases < 2L - 1
   fb.kthr = 0;
-  while ((2 * fb.kthr + 1) * 64 < 2 * L - 1) ++fb.kthr;
+  while ((2 * fb.kthr + 1) * kWideAliases < 2 * L - 1) ++fb.kthr;
   for (int q1 = L; q1 > 0; q1 -= fb.b) {
     const int q0 = std::max(0, q1 - fb.b);
     fb.q0.push_back(q0);
