@@ -17,8 +17,9 @@ sampling  colatitude placements: the equiangular set (Eq. equiangular_set),
           the alternating vector (Eq. sampling_latitude) and the
           condition-number-minimising greedy placement (Sec. III-D).
 sht       inverse SHT (Eq. f_inverse_SHT, Procedure 2), forward SHT
-          (Procedure 1, literally in the spatial domain), both adjoints, the
-          dense sampled-harmonic matrix for tiny L, and error metrics
+          (alias removal in the sample domain, descending |m|, from Eqs.
+          gtof_inverse and signal_update), both adjoints, the dense
+          sampled-harmonic matrix for tiny L, and error metrics
           (Eqs. exp1:errors, exp2:errors).
 
 Functions whose parity is not pinned by an independent check say
