@@ -99,13 +99,14 @@ struct GemmDesc {
 };
 
 struct GemmTask {
-  int32_t desc, mt, nt, pad;
+  int32_t desc, mt, nt, pad;  // pad: int8 apply tasks, the row tile's leading all-zero k-steps
 };
 
 // Inverse apply on int8 digit splits (ozaki.hip): Y = A X for one slot.
 struct OzDesc {
   const int8_t* A;     // digit plane 0 of A (row-major, leading dimension Kp); plane p at A + p * planeA
   const int32_t* ea;   // row exponents
+  const int32_t* rowmap;  // ring of each digit row (rows sorted by sin theta)
   const int8_t* X;     // digit plane 0 of X (column-major, leading dimension ldX); plane q at X + q * planeX
   const int32_t* xe;   // column exponents
   double* C;           // Y (row-major, leading dimension ldc)
@@ -230,7 +231,12 @@ struct Plan {
   // the number of digits, 0 when off; d_A (FP64) stays for the adjoint
   int oz = 0;
   std::vector<int64_t> oz_offA8;  // byte offset of each slot's digit planes in d_A8
-  DevBuf d_A8, d_Aexp, d_ozoff;
+  // digit rows are the rings sorted by sin theta (d_ozrow: row -> ring), so
+  // that each 64-row tile's negligible Legendre values form one prefix of
+  // all-zero 64-deep k-steps; oz_kstart[slot * tiles + tile] is the tile's
+  // first k-step with a nonzero digit
+  std::vector<int32_t> oz_kstart;
+  DevBuf d_A8, d_Aexp, d_ozoff, d_ozrow, d_ozkstart;
   DevBuf w_X8, w_Xexp;            // per-call digits and exponents of the right-hand sides
   DevBuf d_rings, d_chirp, d_twiddle, d_chirp_tab;
   std::vector<int32_t> h_ring_logM;

@@ -42,9 +42,11 @@
 // 16-byte chunks XOR-swizzled by (column / 4) % 4, so the 16 lanes of a k
 // group read 16 distinct bank quads.
 
+#include <algorithm>
 #include <climits>
 #include <cstdlib>
 
+#include "host_util.hpp"
 #include "xform.hpp"
 
 namespace osht {
@@ -78,30 +80,36 @@ __device__ __forceinline__ int exp_above(double v) {
 }
 
 // Plan: A_m (FP64, column-major L x K, leading dimension ldA) -> digits.
-// One workgroup per (64-row tile, slot).  Thread t handles row t / 4 and,
-// in every 64 columns, the 16 columns 16 (t % 4) .. +15: it takes the row
-// maximum over them, then digits them and stores each plane's 16 bytes as
-// one vector, so four consecutive threads write 64 contiguous bytes.
+// Digit row r holds ring rowmap[r].  One workgroup per (64-row tile, slot).
+// Thread t handles row t / 4 and, in every 64 columns, the 16 columns
+// 16 (t % 4) .. +15: it takes the row maximum over them, then digits them
+// and stores each plane's 16 bytes as one vector, so four consecutive
+// threads write 64 contiguous bytes.  The tile's first 64-deep k-step with
+// a nonzero digit goes to kstart[slot * gridDim.x + tile] (Kp / 64 when
+// every digit of the tile is zero).
 template <int S>
 __global__ __launch_bounds__(256) void oz_split_a_kernel(const Slot* __restrict__ slots, const double* __restrict__ A,
                                                          int L, int Mp, const int64_t* __restrict__ offA8,
-                                                         int8_t* __restrict__ A8, int32_t* __restrict__ Aexp) {
+                                                         const int32_t* __restrict__ rowmap, int8_t* __restrict__ A8,
+                                                         int32_t* __restrict__ Aexp, int32_t* __restrict__ kstart) {
   __shared__ double red[64][4];
+  __shared__ int first;
   const int slot = blockIdx.y, m0 = blockIdx.x * 64;
   const Slot sl = slots[slot];
   const int Kp = (sl.K + 63) / 64 * 64;
   const int t = threadIdx.x, row = t >> 2, j = t & 3;
   const int r = m0 + row;
   const double* Ac = A + sl.offA;
+  if (t == 0) first = Kp / 64;
   double mx = 0.0;
   // out-of-range entries load a valid one and are dropped by a select, so
   // that the 16 loads of a step are issued together
-  const int rr = min(r, L - 1);
+  const int rr = rowmap[min(r, L - 1)];
   if (r < L) {
     for (int k0 = 16 * j; k0 < sl.K; k0 += 64) {
       double v[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = fabs(Ac[r + (int64_t)min(k0 + i, sl.K - 1) * sl.ldA]);
+      for (int i = 0; i < 16; ++i) v[i] = fabs(Ac[rr + (int64_t)min(k0 + i, sl.K - 1) * sl.ldA]);
 #pragma unroll
       for (int i = 0; i < 16; ++i) mx = fmax(mx, k0 + i < sl.K ? v[i] : 0.0);
     }
@@ -131,7 +139,13 @@ __global__ __launch_bounds__(256) void oz_split_a_kernel(const Slot* __restrict_
     for (int p = 0; p < S; ++p)
       *reinterpret_cast<v4i*>(out + (int64_t)p * Mp * Kp + ((int64_t)(r >> 4) * (Kp >> 6) + (k0 >> 6)) * 1024 +
                               (r & 15) * 64 + (k0 & 63)) = w[p];
+    bool nz = false;
+#pragma unroll
+    for (int p = 0; p < S; ++p) nz = nz || (w[p][0] | w[p][1] | w[p][2] | w[p][3]) != 0;
+    if (nz) atomicMin(&first, k0 >> 6);
   }
+  __syncthreads();
+  if (t == 0) kstart[(int64_t)slot * gridDim.x + blockIdx.x] = first;
 }
 
 // Per call: slot-layout right-hand sides X[slot][row][col] (FP64, rows
@@ -328,14 +342,16 @@ __global__ __launch_bounds__(256) void oz_apply_kernel(const OzDesc* __restrict_
   const int m0 = tk.mt * kOzTile, n0 = tk.nt * kOzTile;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int li = lane & 15, kq = lane >> 4;
-  const int nk = d.Kp / 64;
+  // k-steps [0, tk.pad) of this row tile hold only zero digits of A (its
+  // rings' negligible Legendre values): they add nothing and are skipped
+  const int nk = d.Kp / 64 - tk.pad;
   // this lane's A chunk: row m0 + 16 wave + li, bytes [16 kq, 16 kq + 16) of
   // each 64-deep step, in the 1 KB block of its 16 rows (steps 1 KB apart)
-  gv4i_ptr asrc = (gv4i_ptr)(d.A + ((int64_t)((m0 >> 4) + wave) * nk) * 1024 + li * 64 + 16 * kq);
+  gv4i_ptr asrc = (gv4i_ptr)(d.A + ((int64_t)((m0 >> 4) + wave) * (d.Kp / 64) + tk.pad) * 1024 + li * 64 + 16 * kq);
   // this thread's B chunk: column n0 + (t >> 2), bytes [16 (t & 3), +16)
   const int bc = t >> 2, bch = t & 3;
   // (steps 4 KB apart in the column tile's blocks)
-  gv4i_ptr bsrc = (gv4i_ptr)(d.X + xblk(n0 + bc, 16 * bch, d.ldX));
+  gv4i_ptr bsrc = (gv4i_ptr)(d.X + xblk(n0 + bc, 16 * bch + 64 * tk.pad, d.ldX));
   const int bpos = bc * 64 + 16 * (bch ^ ((bc >> 2) & 3));
   v4i acc[4][S];
 #pragma unroll
@@ -345,9 +361,11 @@ __global__ __launch_bounds__(256) void oz_apply_kernel(const OzDesc* __restrict_
   // the epilogue's row and column exponents, loaded before the k loop
   // (clamped indices; the unused ones are dropped): guarded one by one in
   // the epilogue, each was waited for in turn after the last product
-  int ear[4], xe[4];
+  int ear[4], xe[4], ring[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) ear[v] = ((gi32_ptr)d.ea)[min(m0 + 16 * wave + 4 * kq + v, d.M - 1)];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) ring[v] = ((gi32_ptr)d.rowmap)[min(m0 + 16 * wave + 4 * kq + v, d.M - 1)];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) xe[cb] = ((gi32_ptr)d.xe)[min(n0 + cb * 16 + li, d.N - 1)];
   v4i a[S], an[S], an2[S], an3[S], bt[S];
@@ -411,7 +429,7 @@ __global__ __launch_bounds__(256) void oz_apply_kernel(const OzDesc* __restrict_
         double y = 0.0;
 #pragma unroll
         for (int dd = 0; dd < S; ++dd) y += ldexp((double)acc[cb][dd][v], e - 7 * (dd + 2));
-        Cg[(int64_t)r * d.ldc + col] = y;
+        Cg[(int64_t)ring[v] * d.ldc + col] = y;
       }
     }
   }
@@ -450,18 +468,35 @@ void build_oz_planes(Plan& p) {
   }
   p.oz_offA8 = off;
   upload(p.d_ozoff, off);
+  // digit rows: the rings in ascending sin(theta) (ties by ring index).  A
+  // ring's Legendre values are negligible below degree ~|m| / sin(theta)
+  // and decay from there towards the pole, so rings of similar sin(theta)
+  // share their run of all-zero leading k-steps
+  std::vector<int32_t> rowmap(p.L);
+  {
+    std::vector<double> sn(p.L);
+    for (int k = 0; k < p.L; ++k) ring_trig(p.L, p.numer[k], nullptr, &sn[k], nullptr, nullptr);
+    for (int k = 0; k < p.L; ++k) rowmap[k] = k;
+    std::stable_sort(rowmap.begin(), rowmap.end(), [&](int32_t a, int32_t b) { return sn[a] < sn[b]; });
+  }
+  upload(p.d_ozrow, rowmap);
+  const int tiles = Mp / kOzTile;
   p.d_A8.alloc((size_t)std::max<int64_t>(tot, 1));
   p.d_Aexp.alloc(sizeof(int32_t) * (size_t)p.nslots * Mp);
-  const dim3 grid((unsigned)(Mp / kOzTile), (unsigned)p.nslots);
+  p.d_ozkstart.alloc(sizeof(int32_t) * (size_t)p.nslots * tiles);
+  const dim3 grid((unsigned)tiles, (unsigned)p.nslots);
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, grid, dim3(256), 0, 0, p.d_slots.as<Slot>(), p.d_A.as<double>(), p.L, Mp,
-                       p.d_ozoff.as<int64_t>(), p.d_A8.as<int8_t>(), p.d_Aexp.as<int32_t>());
+                       p.d_ozoff.as<int64_t>(), p.d_ozrow.as<int32_t>(), p.d_A8.as<int8_t>(), p.d_Aexp.as<int32_t>(),
+                       p.d_ozkstart.as<int32_t>());
   };
   if (S == 6) go(oz_split_a_kernel<6>);
   else if (S == 8) go(oz_split_a_kernel<8>);
   else throw Error{OSHT_ENOTSUP, "unsupported number of int8 digits"};
   OSHT_HIP(hipGetLastError());
   OSHT_HIP(hipDeviceSynchronize());
+  p.oz_kstart.assign((size_t)p.nslots * tiles, 0);
+  OSHT_HIP(hipMemcpy(p.oz_kstart.data(), p.d_ozkstart.p, sizeof(int32_t) * p.oz_kstart.size(), hipMemcpyDeviceToHost));
 }
 
 void oz_descs(const Plan& p, int64_t B, const double* Y, int8_t* X8, const int32_t* Xexp, std::vector<OzDesc>& descs,
@@ -477,6 +512,7 @@ void oz_descs(const Plan& p, int64_t B, const double* Y, int8_t* X8, const int32
     const int Kp = (int)ceil_div(sl.K, kOzTile) * kOzTile;
     d.A = p.d_A8.as<int8_t>() + p.oz_offA8[i];
     d.ea = p.d_Aexp.as<int32_t>() + (int64_t)i * Mp;
+    d.rowmap = p.d_ozrow.as<int32_t>();
     d.X = X8 + (int64_t)i * S * Np * Kx;
     d.xe = Xexp + (int64_t)i * Np;
     d.C = const_cast<double*>(Y) + (int64_t)i * p.L * ncols;
@@ -488,8 +524,10 @@ void oz_descs(const Plan& p, int64_t B, const double* Y, int8_t* X8, const int32
     d.ldX = Kx;
     d.ldc = ncols;
     descs.push_back(d);
-    for (int a = 0; a < Mp / kOzTile; ++a)
-      for (int c = 0; c < Np / kOzTile; ++c) tasks.push_back(GemmTask{i, a, c, 0});
+    for (int a = 0; a < Mp / kOzTile; ++a) {
+      const int k0 = p.oz_kstart[(size_t)i * (Mp / kOzTile) + a];  // leading all-zero k-steps
+      for (int c = 0; c < Np / kOzTile; ++c) tasks.push_back(GemmTask{i, a, c, k0});
+    }
   }
 }
 

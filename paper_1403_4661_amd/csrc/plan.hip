@@ -378,7 +378,7 @@ __global__ void narrow_kernel(const double* __restrict__ src, float* __restrict_
 int64_t Plan::device_bytes() const {
   size_t n = 0;
   for (const DevBuf* b : {&d_cos, &d_sin, &d_cosh, &d_sinh, &d_slots, &d_A, &d_Q, &d_A32, &d_Q32, &d_rings, &d_chirp,
-                          &d_twiddle, &d_chirp_tab, &w_X, &w_Y, &w_H, &w_T, &w_D, &d_status, &d_A8, &d_Aexp, &d_ozoff, &w_X8, &w_Xexp,
+                          &d_twiddle, &d_chirp_tab, &w_X, &w_Y, &w_H, &w_T, &w_D, &d_status, &d_A8, &d_Aexp, &d_ozoff, &d_ozrow, &d_ozkstart, &w_X8, &w_Xexp,
                           &fb.d_slot_list, &fb.d_lev_ptr, &fb.d_unk_slot, &fb.d_unk_r, &fb.d_unk_m, &fb.d_src_ptr,
                           &fb.d_src_slot, &fb.d_src_row, &fb.d_src_m, &fb.d_w_ptr, &fb.d_w_col, &fb.d_w_val,
                           &fb.d_wide_slot, &fb.d_wide_row, &fb.d_wt_ptr, &fb.d_wt_row, &fb.d_wt_val, &fb.d_minv,
