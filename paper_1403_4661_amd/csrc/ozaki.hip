@@ -497,6 +497,9 @@ void build_oz_planes(Plan& p) {
   OSHT_HIP(hipDeviceSynchronize());
   p.oz_kstart.assign((size_t)p.nslots * tiles, 0);
   OSHT_HIP(hipMemcpy(p.oz_kstart.data(), p.d_ozkstart.p, sizeof(int32_t) * p.oz_kstart.size(), hipMemcpyDeviceToHost));
+  // OSHT_OZ_KSKIP=0: every task runs its full k loop (tests compare the two)
+  if (const char* e = std::getenv("OSHT_OZ_KSKIP"))
+    if (std::atoi(e) == 0) std::fill(p.oz_kstart.begin(), p.oz_kstart.end(), 0);
 }
 
 void oz_descs(const Plan& p, int64_t B, const double* Y, int8_t* X8, const int32_t* Xexp, std::vector<OzDesc>& descs,

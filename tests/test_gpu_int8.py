@@ -80,6 +80,25 @@ def test_int8_inverse_repeatable_and_zero_maps():
     assert relmax(a[[0, 2]], __import__("oracle").sht.inverse(oplan(65), flm[[0, 2]])) < TOL_INV["i8x6"]
 
 
+@pytest.mark.parametrize("L,B,seed", [(256, 4, 12), (1024, 2, 13)])
+def test_int8_zero_steps_skip_bit_identical(L, B, seed, monkeypatch):
+    """The digit rows are the rings sorted by sin(theta), and each 64-row
+    tile starts its k loop at its first k-step holding a nonzero digit.  The
+    steps it skips hold zero digits only, so the result equals that of the
+    full k loop bit for bit (OSHT_OZ_KSKIP=0 builds a plan without the
+    skip)."""
+    from paper_1403_4661_amd import Plan
+    x = to_dev(inputs.coeffs(L, B, seed=seed, weighted=True))
+    p = Plan(L, 0, precision="i8x6")
+    a = to_host(p.inverse(x))
+    del p
+    monkeypatch.setenv("OSHT_OZ_KSKIP", "0")
+    q = Plan(L, 0, precision="i8x6")
+    b = to_host(q.inverse(x))
+    del q
+    assert np.array_equal(a, b)
+
+
 def test_int8_round_trip_headline_size():
     """L = 1024, batch 16, headline input: inverse then forward on one I8X6
     plan returns the coefficients to <= 1e-6 (the FP32 inverse alone gives
