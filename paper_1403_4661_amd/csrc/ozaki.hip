@@ -22,7 +22,10 @@
 // 16 rows x 64 k (k contiguous within a row): block (i / 16, k / 64) at
 // ((i / 16) (Kp / 64) + k / 64) * 1024, entry (i % 16) * 64 + k % 64, so one
 // wave's load of a k step (16 rows x 64 bytes) is one contiguous kilobyte;
-// e_i at Aexp[slot * Mp + i].  X digits (per call): per slot, plane q at
+// e_i at Aexp[slot * Mp + i].  Digit row i is ring rowmap[i], the rings in
+// ascending sin(theta), and a task starts its k loop at its row tile's
+// first k step holding a nonzero digit (GemmTask::pad).  X digits (per
+// call): per slot, plane q at
 // slot * S * Np * Kx + q * Np * Kx, Np = the slot columns rounded up to 64,
 // Kx = L rounded up to 64, in 4 KB blocks of 64 columns x 64 k (k contiguous
 // within a column): block (c / 64, k / 64) at ((c / 64) (Kx / 64) + k / 64)
