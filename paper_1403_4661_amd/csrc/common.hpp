@@ -235,8 +235,14 @@ struct Plan {
   // that each 64-row tile's negligible Legendre values form one prefix of
   // all-zero 64-deep k-steps; oz_kstart[slot * tiles + tile] is the tile's
   // first k-step with a nonzero digit
-  std::vector<int32_t> oz_kstart;
+  std::vector<int32_t> oz_kstart, oz_rowmap;
   DevBuf d_A8, d_Aexp, d_ozoff, d_ozrow, d_ozkstart;
+  // per ring k: every order |m| >= ring_cut[k] has all its Legendre values
+  // on ring k below 2^-80, so it adds nothing to ring k's bins in FP64; the
+  // fold stops there and the int8 apply leaves out row tiles made only of
+  // such rings (built from the FP64 A_m; OSHT_RING_CUT=0 keeps every order)
+  std::vector<int32_t> h_ring_cut;
+  DevBuf d_ring_cut;
   DevBuf w_X8, w_Xexp;            // per-call digits and exponents of the right-hand sides
   DevBuf d_rings, d_chirp, d_twiddle, d_chirp_tab;
   std::vector<int32_t> h_ring_logM;

@@ -438,20 +438,25 @@ __device__ __forceinline__ void analysis_body(const RingArgs& a, int k0, int npa
 // list is split into C contiguous chunks whose partial sums are added in
 // chunk order (fixed summation order, deterministic).
 // YT: double, or float for the FP32 inverse apply's output.
+// ring_cut[k] (null: L): only orders |m| < ring_cut[k] reach ring k above
+// 2^-80 (the rows of the others are neither read nor, on int8 plans,
+// written).
 template <class YT, int NT>
-__global__ __launch_bounds__(NT) void fold_kernel(const YT* __restrict__ Y, cplx* __restrict__ H, int L, int B,
-                                                  int spin0, int ncols) {
+__global__ __launch_bounds__(NT) void fold_kernel(const YT* __restrict__ Y, cplx* __restrict__ H,
+                                                  const int32_t* __restrict__ ring_cut, int L, int B, int spin0,
+                                                  int ncols) {
   typedef typename std::conditional<std::is_same<YT, float>::value, float2, double2>::type YT2;
   __shared__ cplx part[NT];
   const int k = blockIdx.x, n = 2 * k + 1;
   const int units = n * B;
   const int C = max(1, NT / units);
   const int64_t base = (int64_t)k * k;
+  const int cut = ring_cut ? ring_cut[k] : L;  // 1 <= cut <= L
   for (int u = threadIdx.x; u < units * C; u += NT) {
     const int c = u / units, rem = u - c * units;
     const int q = rem / B, b = rem - q * B;
-    const int mstart = q - ((q + L - 1) / n) * n;  // smallest m >= -(L-1) congruent to q
-    const int cnt = (L - 1 - mstart) / n + 1;
+    const int mstart = q - ((q + cut - 1) / n) * n;  // smallest m > -cut congruent to q
+    const int cnt = mstart <= cut - 1 ? (cut - 1 - mstart) / n + 1 : 0;
     const int i0 = (int)((int64_t)cnt * c / C), i1 = (int)((int64_t)cnt * (c + 1) / C);
     cplx h = {0.0, 0.0};
     for (int i = i0; i < i1; ++i) {
@@ -757,11 +762,12 @@ void launch_fold(const Plan& p, const double* Y, double* H, int64_t B, hipStream
   // FP32 plans: the inverse apply wrote its output in FP32
   if (p.fp32)
     hipLaunchKernelGGL((fold_kernel<float, kFoldThreads>), dim3(p.L), dim3(kFoldThreads), 0, st,
-                       reinterpret_cast<const float*>(Y), reinterpret_cast<cplx*>(H), p.L, (int)B,
-                       p.spin == 0 ? 1 : 0, p.ncols_per_map * (int)B);
+                       reinterpret_cast<const float*>(Y), reinterpret_cast<cplx*>(H), p.d_ring_cut.as<int32_t>(), p.L,
+                       (int)B, p.spin == 0 ? 1 : 0, p.ncols_per_map * (int)B);
   else
     hipLaunchKernelGGL((fold_kernel<double, kFoldThreads>), dim3(p.L), dim3(kFoldThreads), 0, st, Y,
-                       reinterpret_cast<cplx*>(H), p.L, (int)B, p.spin == 0 ? 1 : 0, p.ncols_per_map * (int)B);
+                       reinterpret_cast<cplx*>(H), p.d_ring_cut.as<int32_t>(), p.L, (int)B, p.spin == 0 ? 1 : 0,
+                       p.ncols_per_map * (int)B);
   OSHT_HIP(hipGetLastError());
 }
 

@@ -483,6 +483,7 @@ void build_oz_planes(Plan& p) {
     std::stable_sort(rowmap.begin(), rowmap.end(), [&](int32_t a, int32_t b) { return sn[a] < sn[b]; });
   }
   upload(p.d_ozrow, rowmap);
+  p.oz_rowmap = rowmap;
   const int tiles = Mp / kOzTile;
   p.d_A8.alloc((size_t)std::max<int64_t>(tot, 1));
   p.d_Aexp.alloc(sizeof(int32_t) * (size_t)p.nslots * Mp);
@@ -530,7 +531,14 @@ void oz_descs(const Plan& p, int64_t B, const double* Y, int8_t* X8, const int32
     d.ldX = Kx;
     d.ldc = ncols;
     descs.push_back(d);
+    const int am = std::abs(sl.m);
     for (int a = 0; a < Mp / kOzTile; ++a) {
+      // a tile whose rings all lie past this order's ring cut is left out:
+      // the fold reads none of its rows
+      bool needed = false;
+      for (int r = a * kOzTile; r < std::min(p.L, (a + 1) * kOzTile); ++r)
+        needed = needed || am < p.h_ring_cut[p.oz_rowmap[r]];
+      if (!needed) continue;
       const int k0 = p.oz_kstart[(size_t)i * (Mp / kOzTile) + a];  // leading all-zero k-steps
       for (int c = 0; c < Np / kOzTile; ++c) tasks.push_back(GemmTask{i, a, c, k0});
     }

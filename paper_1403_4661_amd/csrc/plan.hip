@@ -378,7 +378,7 @@ __global__ void narrow_kernel(const double* __restrict__ src, float* __restrict_
 int64_t Plan::device_bytes() const {
   size_t n = 0;
   for (const DevBuf* b : {&d_cos, &d_sin, &d_cosh, &d_sinh, &d_slots, &d_A, &d_Q, &d_A32, &d_Q32, &d_rings, &d_chirp,
-                          &d_twiddle, &d_chirp_tab, &w_X, &w_Y, &w_H, &w_T, &w_D, &d_status, &d_A8, &d_Aexp, &d_ozoff, &d_ozrow, &d_ozkstart, &w_X8, &w_Xexp,
+                          &d_twiddle, &d_chirp_tab, &w_X, &w_Y, &w_H, &w_T, &w_D, &d_status, &d_A8, &d_Aexp, &d_ozoff, &d_ozrow, &d_ozkstart, &d_ring_cut, &w_X8, &w_Xexp,
                           &fb.d_slot_list, &fb.d_lev_ptr, &fb.d_unk_slot, &fb.d_unk_r, &fb.d_unk_m, &fb.d_src_ptr,
                           &fb.d_src_slot, &fb.d_src_row, &fb.d_src_m, &fb.d_w_ptr, &fb.d_w_col, &fb.d_w_val,
                           &fb.d_wide_slot, &fb.d_wide_row, &fb.d_wt_ptr, &fb.d_wt_row, &fb.d_wt_val, &fb.d_minv,
@@ -386,6 +386,40 @@ int64_t Plan::device_bytes() const {
     n += b->bytes;
   for (const auto& t : tabs) n += t->bytes();
   return (int64_t)n;
+}
+
+// One workgroup per slot: the largest |A_m[k, l]| over the degrees of each
+// ring k; orders whose row reaches 2^-80 raise ring k's cut to |m| + 1.  The
+// values left out sum to below 2^-80 sum_l |x_l| per bin, far under FP64
+// resolution of bins of that scale (Sec. III-F: on a ring near a pole
+// P_l^m(theta) decays exponentially once |m| > l sin(theta)).
+__global__ __launch_bounds__(256) void ring_cut_kernel(const Slot* __restrict__ slots, const double* __restrict__ A,
+                                                       int L, int32_t* __restrict__ cut) {
+  const Slot sl = slots[blockIdx.x];
+  const int am = sl.m < 0 ? -sl.m : sl.m;
+  const double* Ac = A + sl.offA;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) {
+    double mx = 0.0;
+    for (int l = 0; l < sl.K; ++l) mx = fmax(mx, fabs(Ac[k + (int64_t)l * sl.ldA]));
+    if (mx >= 0x1p-80) atomicMax(&cut[k], am + 1);
+  }
+}
+
+void build_ring_cut(Plan& p) {
+  std::vector<int32_t> cut(p.L, 0);
+  const char* e = std::getenv("OSHT_RING_CUT");
+  if (e && std::atoi(e) == 0) {
+    std::fill(cut.begin(), cut.end(), p.L);
+  } else {
+    upload(p.d_ring_cut, cut);
+    hipLaunchKernelGGL(ring_cut_kernel, dim3((unsigned)p.nslots), dim3(256), 0, 0, p.d_slots.as<Slot>(),
+                       p.d_A.as<double>(), p.L, p.d_ring_cut.as<int32_t>());
+    OSHT_HIP(hipGetLastError());
+    OSHT_HIP(hipMemcpy(cut.data(), p.d_ring_cut.p, sizeof(int32_t) * p.L, hipMemcpyDeviceToHost));
+    for (int32_t& c : cut) c = std::max(c, 1);  // order 0 always stays
+  }
+  p.h_ring_cut = cut;
+  upload(p.d_ring_cut, cut);
 }
 
 void build_plan(Plan& p) {
@@ -438,6 +472,8 @@ void build_plan(Plan& p) {
                        p.d_sinh.as<double>(), p.d_slots.as<Slot>(), p.d_A.as<double>());
   }
   OSHT_HIP(hipGetLastError());
+  // the fold of every inverse from here on (the self-check's included) reads it
+  build_ring_cut(p);
   // Newton-Schulz inverses, in chunks bounded by a scratch budget
   DevBuf scratch;
   const int64_t budget = (int64_t)1 << 28;  // doubles (2 GiB)
