@@ -99,6 +99,25 @@ def test_int8_zero_steps_skip_bit_identical(L, B, seed, monkeypatch):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("precision", ["i8x6", "fp64"])
+def test_ring_cut_changes_only_rounding(precision, monkeypatch):
+    """Orders whose Legendre values on a ring all lie below 2^-80 are left out
+    of that ring's fold (and, on int8 plans, of the apply's row tiles).  What
+    they would add is below FP64 resolution: the inverse agrees with a plan
+    that keeps every order (OSHT_RING_CUT=0) to rounding, relative to max |f|."""
+    from paper_1403_4661_amd import Plan
+    L, B = 1024, 2
+    x = to_dev(inputs.coeffs(L, B, seed=14, weighted=True))
+    p = Plan(L, 0, precision=precision)
+    a = to_host(p.inverse(x))
+    del p
+    monkeypatch.setenv("OSHT_RING_CUT", "0")
+    q = Plan(L, 0, precision=precision)
+    b = to_host(q.inverse(x))
+    del q
+    assert relmax(a, b) < 1e-14
+
+
 def test_int8_round_trip_headline_size():
     """L = 1024, batch 16, headline input: inverse then forward on one I8X6
     plan returns the coefficients to <= 1e-6 (the FP32 inverse alone gives
