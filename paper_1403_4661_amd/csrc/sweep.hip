@@ -39,8 +39,12 @@ namespace {
 
 // One thread per (row r, complex column cc = sgn * B + b): both doubles of
 // the complex RHS entry, with the alias search shared by re and im.
+// ring_cut: orders |m'| >= ring_cut[k] have every Legendre value on ring k
+// below 2^-80, so their alias values there are below FP64 resolution of the
+// bin and are not subtracted.
 __global__ __launch_bounds__(256) void block_gather_kernel(Geo g, const Slot* __restrict__ slots,
                                                            const int32_t* __restrict__ slot_list, int q1, int kthr,
+                                                           const int32_t* __restrict__ ring_cut,
                                                            const double2* __restrict__ H, const double* __restrict__ Y,
                                                            double2* __restrict__ X) {
   const int slot = slot_list[blockIdx.y];
@@ -57,6 +61,7 @@ __global__ __launch_bounds__(256) void block_gather_kernel(Geo g, const Slot* __
   if (k < kthr) return;  // many aliases: wide_gather_kernel
   const int bin = pmod(m, n);
   double2 v = H[((int64_t)k * k + bin) * g.B + b];
+  const int cut = ring_cut[k];
   const int start = bin - ((bin + g.L - 1) / n) * n;
   // only orders solved in earlier blocks (|m'| >= q1); four loads in flight,
   // an excluded entry loading Y[0] and subtracting nothing, so the
@@ -68,7 +73,7 @@ __global__ __launch_bounds__(256) void block_gather_kernel(Geo g, const Slot* __
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int q = mp + t * n, aq = q < 0 ? -q : q;
-      use[t] = q != m && aq >= q1;
+      use[t] = q != m && aq >= q1 && aq < cut;
       a[t] = *reinterpret_cast<const double2*>(Y + (use[t] ? alias_index(g, slots, q, k, b, 0) : 0));
     }
 #pragma unroll
@@ -81,7 +86,7 @@ __global__ __launch_bounds__(256) void block_gather_kernel(Geo g, const Slot* __
   }
   for (; mp <= g.L - 1; mp += n) {
     const int amp = mp < 0 ? -mp : mp;
-    if (mp == m || amp < q1) continue;
+    if (mp == m || amp < q1 || amp >= cut) continue;
     const double2 a = *reinterpret_cast<const double2*>(Y + alias_index(g, slots, mp, k, b, 0));
     v.x -= a.x;
     v.y -= a.y;
@@ -103,6 +108,7 @@ constexpr int kWideAliases = 32;
 __global__ __launch_bounds__(kWideThreads) void wide_gather_kernel(Geo g, const Slot* __restrict__ slots,
                                                                    const int32_t* __restrict__ wide_slot,
                                                                    const int32_t* __restrict__ wide_row, int q1,
+                                                                   const int32_t* __restrict__ ring_cut,
                                                                    const double2* __restrict__ H,
                                                                    const double* __restrict__ Y,
                                                                    double2* __restrict__ X) {
@@ -124,6 +130,7 @@ __global__ __launch_bounds__(kWideThreads) void wide_gather_kernel(Geo g, const 
       k = (m < 0 ? -m : m) + r;
       const int n = 2 * k + 1;
       bin = pmod(m, n);
+      const int cut = ring_cut[k];  // as in block_gather_kernel
       const int start = bin - ((bin + g.L - 1) / n) * n;
       const int step = C * n;
       int mp = start + chunk * n;
@@ -133,7 +140,7 @@ __global__ __launch_bounds__(kWideThreads) void wide_gather_kernel(Geo g, const 
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int q = mp + t * step, aq = q < 0 ? -q : q;
-          use[t] = q != m && aq >= q1;  // then |q| > k and the alias row exists
+          use[t] = q != m && aq >= q1 && aq < cut;  // then |q| > k and the alias row exists
           a[t] = *reinterpret_cast<const double2*>(Y + (use[t] ? alias_index(g, slots, q, k, b, 0) : 0));
         }
 #pragma unroll
@@ -144,7 +151,7 @@ __global__ __launch_bounds__(kWideThreads) void wide_gather_kernel(Geo g, const 
       }
       for (; mp <= g.L - 1; mp += step) {
         const int amp = mp < 0 ? -mp : mp;
-        if (mp == m || amp < q1) continue;
+        if (mp == m || amp < q1 || amp >= cut) continue;
         const double2 a = *reinterpret_cast<const double2*>(Y + alias_index(g, slots, mp, k, b, 0));
         acc.x += a.x;
         acc.y += a.y;
@@ -755,15 +762,16 @@ void run_forward_blocked(Plan& p, const double* f, double* flm, int64_t B, hipSt
       ProfScope ps(p.prof, "gather_forward", st);
       hipLaunchKernelGGL(block_gather_kernel, dim3((unsigned)ceil_div((int64_t)p.L * (g.ncols / 2), 256), ns), dim3(256),
                          0, st, g, p.d_slots.as<Slot>(), fb.d_slot_list.as<int32_t>() + fb.slot_ptr[blk], fb.q1[blk],
-                         fb.kthr, reinterpret_cast<const double2*>(p.w_H.as<double>()), p.w_Y.as<double>(),
+                         fb.kthr, p.d_ring_cut.as<int32_t>(), reinterpret_cast<const double2*>(p.w_H.as<double>()),
+                         p.w_Y.as<double>(),
                          reinterpret_cast<double2*>(p.w_X.as<double>()));
       OSHT_HIP(hipGetLastError());
       const int nwide = fb.wide_ptr[blk + 1] - fb.wide_ptr[blk];
       if (nwide > 0) {
         hipLaunchKernelGGL(wide_gather_kernel, dim3((unsigned)nwide), dim3(kWideThreads), 0, st, g, p.d_slots.as<Slot>(),
                            fb.d_wide_slot.as<int32_t>() + fb.wide_ptr[blk], fb.d_wide_row.as<int32_t>() + fb.wide_ptr[blk],
-                           fb.q1[blk], reinterpret_cast<const double2*>(p.w_H.as<double>()), p.w_Y.as<double>(),
-                           reinterpret_cast<double2*>(p.w_X.as<double>()));
+                           fb.q1[blk], p.d_ring_cut.as<int32_t>(), reinterpret_cast<const double2*>(p.w_H.as<double>()),
+                           p.w_Y.as<double>(), reinterpret_cast<double2*>(p.w_X.as<double>()));
         OSHT_HIP(hipGetLastError());
       }
     }
