@@ -88,8 +88,10 @@ def test_forward_random_samples_matches_oracle(L):
 @pytest.mark.parametrize("s", [2, -2, 1])
 def test_spin_forward_small_L(s):
     """Spin forward (Sec. III-G) at L = 6, where the order-wise elimination is
-    still accurate; larger L is unstable on this scheme in FP64 for both the
-    oracle and the GPU."""
+    still accurate.  At larger L it is unstable on this scheme in FP64, in the
+    oracle and on the GPU alike: its error grows by orders of magnitude per
+    few degrees, and plans refuse the spin forward once their self-check
+    fails."""
     from oracle import sht
     L = 6
     flm = inputs.coeffs(L, 2, seed=11, spin=s)
